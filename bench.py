@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of symbolic-regression fitness evaluation on one MI355X.
+
+A step is one pass of the whole evaluation path over the resident workload:
+validate + compile every tree (plan kernel), evaluate every tree on every
+data point and reduce the squared errors (evaluation kernel), write one
+fitness per tree (finalize). The metric is GPops/s = sum of tree lengths x
+data points / time (Langdon's measure as used in the paper's §V-C, with one
+generation per step). Inputs are seeded synthetic data of the workload's
+shape, already in device memory when the timed region starts.
+
+Prints one JSON line. Extra objects:
+  roofline      the evaluation kernel against the vector-ALU issue peak;
+  cpu_baseline  the CPU oracle timed on the host (a baseline, not a target).
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GPops/s (tree nodes × points / s), fwd MSE and fwd+adjoint vs plain fwd"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes, one fp32 lane-op per lane per clock (non-packed), 2.4 GHz
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "tanh", "exp", "log", "max", "min", "tan")
+HELPER = {7: 1.0, 11: 1.0}   # the exp and tan micro-kernels carry one extra sub / mul per step
+EVAL_SOURCES = ("eval_impl.h", "tgp_isa.h", "tgp_kernels.h")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hybrid", choices=["plain", "hybrid", "dataparallel", "batched", "grad"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--save-cfg", default=None, help="write the chosen launch configuration (JSON) here")
+    ap.add_argument("--load-cfg", default=None, help="use this launch configuration (JSON) instead of tuning")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def eval_source_hash():
+    h = hashlib.sha256()
+    for f in EVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_17168_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, src_hash):
+    """HBM bytes per evaluation launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current evaluation-kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"eval_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"source hash:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"bytes per launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != src_hash:
+        return None
+    return float(m_bytes.group(1))
+
+
+def op_costs(tgp):
+    """Cost of each operator in vector-ALU issue slots, measured live: rate(add) / rate(op)."""
+    from paper_2501_17168_amd import _lib
+    rates = [_lib.op_rate(o) for o in range(len(OP_NAMES))]
+    base = rates[0]
+    return [max(1.0, base / r - HELPER.get(o, 0.0)) for o, r in enumerate(rates)], base
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2501_17168_amd as tgp
+    from paper_2501_17168_amd import _lib
+
+    dev = torch.device("cuda:0")
+    w = synth.workload(args.workload)
+    pop = tgp.Population(*(torch.from_numpy(a).to(dev) for a in (w.type, w.value, w.size)))
+    X = torch.from_numpy(w.X).to(dev)
+    if w.Y is not None:
+        Y = torch.from_numpy(w.Y).to(dev)
+    else:
+        # targets: the hidden trees' predictions (computed by the library itself) plus noise
+        hidden = tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in w.hidden))
+        _, hp = tgp.eval_multi_output(hidden, X, None, n_out=1, want_pred=True)
+        Y = (hp[:, 0, :] + torch.from_numpy(w.noise).to(dev)).contiguous()
+    torch.cuda.synchronize()
+
+    lengths = w.lengths()
+    sum_len = int(lengths.sum())
+    gpops_per_step = float(sum_len) * w.D
+
+    cfg = None
+    if args.load_cfg:
+        with open(args.load_cfg) as f:
+            cfg = json.load(f)
+    elif not args.no_autotune:
+        cfg = tgp.autotune(pop, X, Y, n_out=w.n_out)
+    if args.save_cfg and cfg:
+        with open(args.save_cfg, "w") as f:
+            json.dump(cfg, f)
+    step_cfg = tgp.cfg(cfg) if cfg else None
+
+    def step():
+        if w.n_out == 1:
+            tgp.eval_mse(pop, X, Y, config=step_cfg)
+        else:
+            tgp.eval_multi_output(pop, X, Y, config=step_cfg)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.profile(True)
+    _lib.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    eval_ms_total, launches = _lib.profile_read()
+    _lib.profile(False)
+    ms_step = ms / args.steps
+    value = gpops_per_step * args.steps / (ms * 1e-3)
+
+    # ---- roofline of the evaluation kernel ----
+    costs, add_rate = op_costs(tgp)
+    t = w.type
+    fn = t >= 2
+    ops = w.value[fn].astype(np.int64)
+    counts = np.bincount(ops, minlength=len(OP_NAMES))
+    ops_per_point = float(np.dot(counts, costs)) + 2.0 * w.P * w.n_out
+    algo_ops = ops_per_point * w.D
+    eval_ms = eval_ms_total / max(launches, 1)
+    achieved = algo_ops / (eval_ms * 1e-3)
+    src_hash = eval_source_hash()
+    traffic = stored_traffic(args.workload, src_hash)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Top/s",
+                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                "kernel": "eval_kernel", "kernel_ms": eval_ms, "algo_ops_per_launch": algo_ops,
+                "op_cost": {n: round(c, 3) for n, c in zip(OP_NAMES, costs)},
+                "add_rate_per_s": add_rate, "eval_source_hash": src_hash}
+
+    # ---- CPU baseline: the oracle on a bounded sample ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        Yh = Y.cpu().numpy()
+        order = np.random.default_rng(0).permutation(w.P)
+        done_len = 0
+        n_trees = 0
+        t0 = time.perf_counter()
+        for p in order:
+            O.mse(w.type, w.value, w.size, w.X, Yh, w.n_out, rows=[int(p)])
+            done_len += int(lengths[p])
+            n_trees += 1
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        cpu = {"value": done_len * w.D / el, "unit": "GPops/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_trees} of {w.P} trees (random order) x all {w.D} points, float64 numpy, "
+                         f"{el:.1f} s single-threaded"}
+
+    out = {"metric": METRIC, "value": value, "unit": "GPops/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
+                      "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
+           "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,186 @@
+/* tgp.h -- symbolic-regression fitness evaluation for tensorized tree GP on gfx950.
+ *
+ * The problem (paper: "Enabling Population-Level Parallelism in Tree-Based
+ * Genetic Programming for GPU Acceleration"):
+ *   - a population of P expression trees in the tensorized prefix encoding of
+ *     §III-A: three row-major [P][row_stride] float32 tensors holding, per
+ *     tree, node types, node values and subtree sizes of the prefix node
+ *     sequence in the first len entries and NaN after them (len = size[0]);
+ *   - a data set of D points with V input variables and n_out targets;
+ *   - one fitness per tree: the squared error of the tree's prediction
+ *     against the targets, averaged over the D points and summed over
+ *     outputs (§III-C first paragraph; Alg. 1 maximises its negation).
+ *   Multi-output trees use Modi nodes (§IV-C): a Modi node adds its function
+ *   value to its output and hands its rightmost child's value to its parent.
+ *
+ * Node encoding used by this library (the paper fixes no codes):
+ *   type 0 = variable (value = input index in [0,V)), 1 = constant,
+ *   2 = function (value = op id), 3+o = Modi node for output o (value = op id).
+ *   op ids: 0 add, 1 sub, 2 mul, 3 protected div (|b| < 1e-6f gives 1),
+ *   4 sin, 5 cos, 6 tanh, 7 exp with the argument clamped to [-20,20],
+ *   8 protected log log(|a| + 1e-6f), 9 max, 10 min (NaN operand ignored),
+ *   11 tan. A binary node computes f(first child, second child); the first
+ *   child sits at index i+1, the second at i+1+size[i+1].
+ *   A tree with no Modi node predicts out[0] = root value and 0 for other
+ *   outputs; a tree with Modi nodes predicts out[o] = sum of its Modi(o)
+ *   contributions (0 if none).
+ *
+ * Conventions for every call below:
+ *   - Pointers inside tgp_pop / tgp_data and all output pointers are DEVICE
+ *     pointers owned by the caller. The library never frees or retains them.
+ *   - Work is enqueued asynchronously on `stream`; evaluation calls allocate
+ *     nothing and never synchronise, so they can be captured in a hipGraph.
+ *   - Errors detectable on the host (null pointers, bad sizes, a workspace
+ *     that is too small, unsupported sizes) return a negative status at once
+ *     and enqueue nothing. Errors in a tree's encoding are found on the
+ *     device: that tree gets a non-zero tree_status and a NaN fitness, and
+ *     the call still returns TGP_OK.
+ *   - `ws` is a caller-owned device workspace of at least
+ *     tgp_workspace_bytes(...) bytes, 256-byte aligned. Its contents are
+ *     scratch between calls; concurrent calls must not share one workspace.
+ *   - Limits: 1 <= Lmax <= 1024, 1 <= V <= 16, 1 <= n_out <= 4, D >= 1.
+ */
+#ifndef TGP_H
+#define TGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tgp_status;
+enum {
+  TGP_OK = 0,
+  TGP_E_ARG = -1,          /* null pointer or invalid scalar argument            */
+  TGP_E_SHAPE = -2,        /* inconsistent sizes or strides                       */
+  TGP_E_WORKSPACE = -4,    /* workspace null, misaligned or smaller than needed   */
+  TGP_E_UNSUPPORTED = -5,  /* sizes beyond the limits listed above                */
+  TGP_E_HIP = -6           /* a HIP runtime call or kernel launch failed          */
+};
+
+/* Per-tree status codes written to tree_status[t] (the smallest applicable):
+ * 0 ok; 1 size[0] not an integer in [1,Lmax]; 2 NaN inside the first len
+ * entries; 3 non-NaN entry at or after len; 4 unknown type code (or Modi
+ * output >= n_out); 5 bad op id; 6 bad variable index; 7 subtree sizes
+ * inconsistent with the prefix sequence. */
+enum { TGP_TREE_OK = 0, TGP_TREE_LEN = 1, TGP_TREE_NAN = 2, TGP_TREE_TAIL = 3,
+       TGP_TREE_TYPE = 4, TGP_TREE_OP = 5, TGP_TREE_VAR = 6, TGP_TREE_SIZE = 7 };
+
+/* Population: row-major [P][row_stride] float32 tensors, first Lmax columns used. */
+typedef struct tgp_pop {
+  const float* type;
+  const float* value;
+  const float* size;
+  int64_t P;
+  int32_t Lmax;
+  int64_t row_stride;      /* >= Lmax, in elements */
+} tgp_pop;
+
+/* Data: X[v*ldx + p] (variable-major), Y[o*ldy + p]; p in [0,D). */
+typedef struct tgp_data {
+  const float* X;
+  int32_t V;
+  int64_t D;
+  int64_t ldx;             /* >= D */
+  const float* Y;          /* may be NULL for prediction-only calls */
+  int32_t n_out;
+  int64_t ldy;             /* >= D when Y is given */
+} tgp_data;
+
+/* Launch configuration. Zero fields mean "default"; a NULL cfg means
+ * "autotuned choice for this shape if tgp_autotune has cached one, else
+ * the built-in default". */
+enum { TGP_MODE_AUTO = 0, TGP_MODE_TREE_MAJOR = 1, TGP_MODE_POINT_MAJOR = 2,
+       TGP_MODE_PERSISTENT = 3 };
+enum { TGP_FLAG_NO_TAIL_CHECK = 1 };   /* skip reading the NaN padding after len */
+typedef struct tgp_cfg {
+  int32_t mode;             /* TGP_MODE_*                                           */
+  int32_t block_waves;      /* waves per workgroup: 1, 2 or 4                       */
+  int32_t points_per_lane;  /* data points per lane: 4 or 8                         */
+  int32_t trees_per_unit;   /* trees handled per work unit (point-major, persistent) */
+  int32_t flags;            /* TGP_FLAG_*                                           */
+} tgp_cfg;
+
+/* Bytes of workspace needed by any call on these shapes (n_out outputs;
+ * want_grad != 0 adds room for tgp_eval_mse_grad). Returns 0 for shapes
+ * the library rejects. */
+size_t tgp_workspace_bytes(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
+                           int32_t want_grad);
+
+/* Validate and plan every tree (§III-A encoding, §III-C evaluation order).
+ * info: optional device int32 [P][6] receiving, per tree,
+ *   (status, len, max stack depth of the reversed-prefix evaluation,
+ *    number of constant nodes, number of Modi nodes, length bucket
+ *    = 0 for len 1 else ceil(log2(len))); all zero except status for an
+ *   invalid tree.
+ * tree_status: optional device int32 [P]. V and n_out bound variable
+ * indices and Modi outputs. */
+tgp_status tgp_plan(const tgp_pop* pop, int32_t V, int32_t n_out, const tgp_cfg* cfg,
+                    int32_t* info, int32_t* tree_status, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* Fitness of every tree: mse[t] = (1/D) sum_p (out_0(x_p) - Y[p])^2 (n_out = 1).
+ * data->n_out must be 1 and data->Y non-null. mse: device float32 [P].
+ * tree_status: optional device int32 [P]. */
+tgp_status tgp_eval_mse(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
+                        float* mse, int32_t* tree_status, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Multi-output evaluation (§IV-C). With data->Y: mse[t] = sum over the
+ * n_out outputs of the mean squared error (mse may be NULL to skip).
+ * pred (optional, device float32): pred[(t*n_out + o)*ldp + p] receives
+ * out_o of tree t at point p (ldp >= D); invalid trees get NaN.
+ * At least one of mse / pred must be non-null. */
+tgp_status tgp_eval_multi_output(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
+                                 float* mse, float* pred, int64_t ldp, int32_t* tree_status,
+                                 void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Fitness and its gradient (not in the paper; reverse-mode sweep over the
+ * prefix tree with subtree values recomputed, nothing stored per point).
+ * grad_mse: optional device float32 [P], upstream dL/dmse_t (NULL = all ones).
+ * grad_value: optional device float32 [P][row_stride], overwritten with
+ *   dL/dvalue (non-zero only at constant nodes; zero elsewhere and for
+ *   invalid trees).
+ * grad_X: optional device float32 [V][ldx], overwritten with
+ *   sum_t dL/dmse_t * dmse_t/dX.
+ * n_out must be 1. mse: device float32 [P]. */
+tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
+                             const float* grad_mse, float* mse, float* grad_value,
+                             float* grad_X, int32_t* tree_status, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Time the candidate launch configurations on this population and data,
+ * keep the fastest in a process-wide cache keyed by the shape, and return
+ * it in *out. Synchronises the stream; not capturable. want_grad selects
+ * the gradient path (reserved; forward configurations are tuned). */
+tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
+                        int32_t want_grad, tgp_cfg* out, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Static description of a status code. */
+const char* tgp_status_str(tgp_status s);
+
+/* ---- measurement helpers (not part of the evaluated method) ----
+ * tgp_op_rate: throughput, in applications per second, of op id `op`
+ *   (0..11) in a straight-line compiled loop (8 independent chains per
+ *   lane, full occupancy) on the current device; the rate relative to add
+ *   is the operator's cost in vector-ALU issue slots. Synchronous; it
+ *   allocates and frees a small device buffer. Returns TGP_E_ARG for a bad
+ *   op or null output.
+ * tgp_profile(enable): while enabled, every forward call records a HIP
+ *   event pair around its evaluation-kernel launch on the caller's stream
+ *   (creating the two events on the host).
+ * tgp_profile_read: waits for the recorded events, returns the summed
+ *   evaluation-kernel time in ms and the number of launches, and clears
+ *   the record. */
+tgp_status tgp_op_rate(int32_t op, double* ops_per_s);
+tgp_status tgp_profile(int32_t enable);
+tgp_status tgp_profile_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGP_H */

@@ -1,0 +1,125 @@
+"""ctypes binding of libtgp.so (the C-ABI declared in include/tgp.h).
+
+Argument marshalling only: every step of the evaluation runs in the
+library's HIP kernels. The library is loaded from this package directory;
+a missing library is an error, never a fallback.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtgp.so")
+
+TGP_OK = 0
+TGP_E_ARG = -1
+TGP_E_SHAPE = -2
+TGP_E_WORKSPACE = -4
+TGP_E_UNSUPPORTED = -5
+TGP_E_HIP = -6
+
+MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT = 0, 1, 2, 3
+FLAG_NO_TAIL_CHECK = 1
+
+# symbols the header declares; the CPU tests check that each one is exported
+EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output",
+           "tgp_eval_mse_grad", "tgp_autotune", "tgp_status_str", "tgp_op_rate", "tgp_profile",
+           "tgp_profile_read")
+
+
+class TgpPop(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_void_p), ("value", ctypes.c_void_p), ("size", ctypes.c_void_p),
+                ("P", ctypes.c_int64), ("Lmax", ctypes.c_int32), ("row_stride", ctypes.c_int64)]
+
+
+class TgpData(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("V", ctypes.c_int32), ("D", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("Y", ctypes.c_void_p), ("n_out", ctypes.c_int32),
+                ("ldy", ctypes.c_int64)]
+
+
+class TgpCfg(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("block_waves", ctypes.c_int32),
+                ("points_per_lane", ctypes.c_int32), ("trees_per_unit", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TgpError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: status {code} ({status_str(code)})")
+
+
+_lib = None
+
+
+def load():
+    """Load libtgp.so once. Raises if it is missing: there is no CPU fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                          f"or `python paper_2501_17168_amd/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    lib.tgp_workspace_bytes.argtypes = [P(TgpPop), P(TgpData), i32, i32]
+    lib.tgp_workspace_bytes.restype = ctypes.c_size_t
+    lib.tgp_plan.argtypes = [P(TgpPop), i32, i32, P(TgpCfg), vp, vp, vp, ctypes.c_size_t, vp]
+    lib.tgp_plan.restype = i32
+    lib.tgp_eval_mse.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp, ctypes.c_size_t, vp]
+    lib.tgp_eval_mse.restype = i32
+    lib.tgp_eval_multi_output.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, ctypes.c_int64, vp, vp,
+                                          ctypes.c_size_t, vp]
+    lib.tgp_eval_multi_output.restype = i32
+    lib.tgp_eval_mse_grad.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                      vp]
+    lib.tgp_eval_mse_grad.restype = i32
+    lib.tgp_autotune.argtypes = [P(TgpPop), P(TgpData), i32, i32, P(TgpCfg), vp, ctypes.c_size_t, vp]
+    lib.tgp_autotune.restype = i32
+    lib.tgp_op_rate.argtypes = [i32, P(ctypes.c_double)]
+    lib.tgp_op_rate.restype = i32
+    lib.tgp_profile.argtypes = [i32]
+    lib.tgp_profile.restype = i32
+    lib.tgp_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
+    lib.tgp_profile_read.restype = i32
+    lib.tgp_status_str.argtypes = [i32]
+    lib.tgp_status_str.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(code):
+    try:
+        return load().tgp_status_str(int(code)).decode()
+    except ImportError:
+        return "library not loaded"
+
+
+def check(code, where):
+    if code != TGP_OK:
+        raise TgpError(code, where)
+
+
+def op_rate(op):
+    """Applications per second of op id `op` in a compiled straight-line loop (device measurement)."""
+    r = ctypes.c_double()
+    check(load().tgp_op_rate(int(op), ctypes.byref(r)), "tgp_op_rate")
+    return r.value
+
+
+def profile(enable):
+    check(load().tgp_profile(int(bool(enable))), "tgp_profile")
+
+
+def profile_read():
+    """(summed evaluation-kernel ms, number of launches) since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    check(load().tgp_profile_read(ctypes.byref(ms), ctypes.byref(n)), "tgp_profile_read")
+    return ms.value, n.value

@@ -1,0 +1,242 @@
+"""Torch-facing wrappers of the C-ABI (same names as the C entry points).
+
+Torch supplies device memory and the current stream; the wrappers only
+check tensor properties, build the ABI structs and call the library.
+Populations are three float32 CUDA tensors [P][Lmax] (type, value, size) in
+the NaN-padded prefix encoding of the paper's §III-A; X is [V][D] float32
+(variable-major), Y is [n_out][D] float32.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import TgpCfg, TgpData, TgpPop, check
+
+__all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output",
+           "eval_mse_grad", "autotune"]
+
+
+def _dev(t, name, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if t.dim() >= 1 and t.stride(-1) != 1:
+        raise ValueError(f"{name} must have unit stride in its last dimension")
+    return t
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Population:
+    """Three [P][Lmax] float32 device tensors sharing one row stride."""
+
+    def __init__(self, type, value, size):
+        for n, t in (("type", type), ("value", value), ("size", size)):
+            _dev(t, n)
+            if t.dim() != 2:
+                raise ValueError(f"{n} must be 2-D [P][Lmax]")
+        if not (type.shape == value.shape == size.shape):
+            raise ValueError("type, value and size must have the same shape")
+        if not (type.stride(0) == value.stride(0) == size.stride(0)):
+            raise ValueError("type, value and size must share one row stride")
+        self.type, self.value, self.size = type, value, size
+
+    @property
+    def P(self):
+        return self.type.shape[0]
+
+    @property
+    def Lmax(self):
+        return self.type.shape[1]
+
+    def abi(self):
+        return TgpPop(self.type.data_ptr(), self.value.data_ptr(), self.size.data_ptr(), self.P, self.Lmax,
+                      max(self.type.stride(0), self.Lmax))
+
+
+def _data(X, Y=None, n_out=None):
+    _dev(X, "X")
+    if X.dim() != 2:
+        raise ValueError("X must be 2-D [V][D]")
+    V, D = X.shape
+    ldy = 0
+    yp = None
+    if Y is not None:
+        _dev(Y, "Y")
+        if Y.dim() == 1:
+            Y = Y.unsqueeze(0)
+        if Y.shape[1] != D:
+            raise ValueError("Y must be [n_out][D] with the same D as X")
+        n_out = Y.shape[0] if n_out is None else n_out
+        if Y.shape[0] != n_out:
+            raise ValueError("Y rows must equal n_out")
+        ldy = Y.stride(0) if Y.shape[0] > 1 else D
+        yp = Y.data_ptr()
+    n_out = 1 if n_out is None else int(n_out)
+    ldx = X.stride(0) if V > 1 else D
+    return TgpData(X.data_ptr(), V, D, ldx, yp, n_out, ldy), Y
+
+
+def cfg(mode=0, block_waves=0, points_per_lane=0, trees_per_unit=0, flags=0):
+    """Launch configuration (zeros = defaults). mode: 0 auto, 1 tree-major, 2 point-major, 3 persistent."""
+    if isinstance(mode, TgpCfg):
+        return mode
+    if isinstance(mode, dict):
+        return TgpCfg(**mode)
+    return TgpCfg(int(mode), int(block_waves), int(points_per_lane), int(trees_per_unit), int(flags))
+
+
+def _cfgp(c):
+    return None if c is None else ctypes.byref(cfg(c))
+
+
+def workspace_bytes(pop, X=None, n_out=1, want_grad=False, V=None, D=None):
+    lib = _lib.load()
+    p = pop.abi()
+    if X is not None:
+        d, _ = _data(X, None, n_out)
+        dp = ctypes.byref(d)
+    else:
+        dp = None
+    n = lib.tgp_workspace_bytes(ctypes.byref(p), dp, int(n_out), int(bool(want_grad)))
+    if n == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_workspace_bytes")
+    return n
+
+
+class Workspace:
+    """A caller-owned device workspace that grows on demand (allocation happens
+    here, outside the library's evaluation calls)."""
+
+    def __init__(self, device="cuda"):
+        self.buf = None
+        self.device = device
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def ptr_size(self, nbytes):
+        b = self.get(nbytes)
+        return ctypes.c_void_p(b.data_ptr()), b.numel()
+
+
+_default_ws = {}
+
+
+def _ws(ws, nbytes, device):
+    if ws is None:
+        key = str(device)
+        ws = _default_ws.setdefault(key, Workspace(device))
+    return ws.ptr_size(nbytes)
+
+
+def plan(pop, V, n_out=1, config=None, ws=None, stream=None):
+    """Validate and plan every tree. Returns (info int32 [P][6], tree_status int32 [P])."""
+    lib = _lib.load()
+    p = pop.abi()
+    dev = pop.type.device
+    info = torch.empty((pop.P, 6), dtype=torch.int32, device=dev)
+    st = torch.empty((pop.P,), dtype=torch.int32, device=dev)
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), None, int(n_out), 0)
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_plan")
+    wp, wn = _ws(ws, nbytes, dev)
+    check(lib.tgp_plan(ctypes.byref(p), int(V), int(n_out), _cfgp(config), ctypes.c_void_p(info.data_ptr()),
+                       ctypes.c_void_p(st.data_ptr()), wp, wn, _stream(stream)), "tgp_plan")
+    return info, st
+
+
+def eval_mse(pop, X, y, config=None, ws=None, out=None, tree_status=None, stream=None):
+    """Fitness (mean squared error) of every tree against y [D] or [1][D]. Returns float32 [P]."""
+    lib = _lib.load()
+    d, _ = _data(X, y, 1)
+    p = pop.abi()
+    mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device) if out is None else out
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), 1, 0)
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_eval_mse")
+    wp, wn = _ws(ws, nbytes, X.device)
+    stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
+    check(lib.tgp_eval_mse(ctypes.byref(p), ctypes.byref(d), _cfgp(config), ctypes.c_void_p(mse.data_ptr()), stp,
+                           wp, wn, _stream(stream)), "tgp_eval_mse")
+    return mse
+
+
+def eval_multi_output(pop, X, Y=None, n_out=None, want_mse=True, want_pred=False, config=None, ws=None,
+                      tree_status=None, stream=None):
+    """Multi-output evaluation. Returns (mse [P] or None, pred [P][n_out][D] or None)."""
+    lib = _lib.load()
+    if Y is None:
+        want_mse = False
+    d, Y = _data(X, Y, n_out)
+    n_out = d.n_out
+    p = pop.abi()
+    D = X.shape[1]
+    mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device) if want_mse else None
+    pred = torch.empty((pop.P, n_out, D), dtype=torch.float32, device=X.device) if want_pred else None
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), n_out, 0)
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_eval_multi_output")
+    wp, wn = _ws(ws, nbytes, X.device)
+    stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
+    check(lib.tgp_eval_multi_output(
+        ctypes.byref(p), ctypes.byref(d), _cfgp(config),
+        ctypes.c_void_p(mse.data_ptr()) if mse is not None else None,
+        ctypes.c_void_p(pred.data_ptr()) if pred is not None else None, D, stp, wp, wn, _stream(stream)),
+        "tgp_eval_multi_output")
+    return mse, pred
+
+
+def eval_mse_grad(pop, X, y, grad_mse=None, want_grad_value=True, want_grad_x=True, config=None, ws=None,
+                  tree_status=None, stream=None):
+    """Fitness and gradients. Returns (mse [P], grad_value [P][Lmax] or None, grad_X [V][D] or None)."""
+    lib = _lib.load()
+    d, _ = _data(X, y, 1)
+    p = pop.abi()
+    mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device)
+    gv = torch.empty((pop.P, pop.type.stride(0)), dtype=torch.float32, device=X.device) if want_grad_value else None
+    gx = torch.empty((X.shape[0], d.ldx), dtype=torch.float32, device=X.device) if want_grad_x else None
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), 1, 1)
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_eval_mse_grad")
+    wp, wn = _ws(ws, nbytes, X.device)
+    gm = None
+    if grad_mse is not None:
+        _dev(grad_mse, "grad_mse")
+        gm = ctypes.c_void_p(grad_mse.data_ptr())
+    stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
+    check(lib.tgp_eval_mse_grad(
+        ctypes.byref(p), ctypes.byref(d), _cfgp(config), gm, ctypes.c_void_p(mse.data_ptr()),
+        ctypes.c_void_p(gv.data_ptr()) if gv is not None else None,
+        ctypes.c_void_p(gx.data_ptr()) if gx is not None else None, stp, wp, wn, _stream(stream)),
+        "tgp_eval_mse_grad")
+    if gv is not None:
+        gv = gv[:, :pop.Lmax]
+    if gx is not None:
+        gx = gx[:, :X.shape[1]]
+    return mse, gv, gx
+
+
+def autotune(pop, X, Y, n_out=None, want_grad=False, ws=None, stream=None):
+    """Time the candidate schedules on this workload and cache the fastest. Returns the chosen cfg dict."""
+    lib = _lib.load()
+    d, _ = _data(X, Y, n_out)
+    p = pop.abi()
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), d.n_out, int(bool(want_grad)))
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_autotune")
+    wp, wn = _ws(ws, nbytes, X.device)
+    out = TgpCfg()
+    check(lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d), d.n_out, int(bool(want_grad)), ctypes.byref(out),
+                           wp, wn, _stream(stream)), "tgp_autotune")
+    return out.as_dict()

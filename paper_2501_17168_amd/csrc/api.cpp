@@ -1,0 +1,324 @@
+// C-ABI entry points: argument checks, workspace layout, launch selection.
+//
+// Every evaluation call enqueues, on the caller's stream and without any
+// allocation or synchronisation:
+//   prep (zero the bucket counters and the work queue)
+//   -> plan (validate, plan figures, compile programs, zero accumulators)
+//   -> [order trees by length bucket, persistent mode only]
+//   -> evaluation kernel -> finalize (fitness and per-tree status).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "tgp.h"
+#include "tgp_autotune.h"
+#include "tgp_kernels.h"
+
+using namespace tgp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kCounters = 64;  // hist[16] | cursor[17] @16 | queue @48
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t info, acc, order, counters, prog, gwork, total;
+};
+
+Layout layout(int64_t P, int Lmax, int64_t grad_bytes) {
+  Layout L{};
+  size_t off = 0;
+  L.info = off; off = align_up(off + (size_t)P * kInfoStride * sizeof(int32_t));
+  L.acc = off; off = align_up(off + (size_t)P * sizeof(double));
+  L.order = off; off = align_up(off + (size_t)P * sizeof(int32_t));
+  L.counters = off; off = align_up(off + kCounters * sizeof(int32_t));
+  L.prog = off; off = align_up(off + (size_t)P * prog_stride(Lmax) * sizeof(uint2));
+  L.gwork = off; off = align_up(off + (size_t)grad_bytes);
+  L.total = off;
+  return L;
+}
+
+tgp_status check_pop(const tgp_pop* pop) {
+  if (!pop) return TGP_E_ARG;
+  if (pop->P < 0) return TGP_E_SHAPE;
+  if (pop->P > 0 && (!pop->type || !pop->value || !pop->size)) return TGP_E_ARG;
+  if (pop->Lmax < 1) return TGP_E_SHAPE;
+  if (pop->Lmax > kMaxLmax) return TGP_E_UNSUPPORTED;
+  if (pop->row_stride < pop->Lmax) return TGP_E_SHAPE;
+  if (pop->P > (int64_t)INT32_MAX) return TGP_E_UNSUPPORTED;
+  return TGP_OK;
+}
+
+tgp_status check_data(const tgp_data* d, bool need_y) {
+  if (!d) return TGP_E_ARG;
+  if (!d->X) return TGP_E_ARG;
+  if (d->V < 1 || d->D < 1) return TGP_E_SHAPE;
+  if (d->V > kMaxV) return TGP_E_UNSUPPORTED;
+  if (d->ldx < d->D) return TGP_E_SHAPE;
+  if (d->n_out < 1) return TGP_E_SHAPE;
+  if (d->n_out > kMaxOut) return TGP_E_UNSUPPORTED;
+  if (need_y && !d->Y) return TGP_E_ARG;
+  if (d->Y && d->ldy < d->D) return TGP_E_SHAPE;
+  return TGP_OK;
+}
+
+tgp_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (!ws) return TGP_E_WORKSPACE;
+  if (((uintptr_t)ws) % kAlign) return TGP_E_WORKSPACE;
+  if (ws_bytes < need) return TGP_E_WORKSPACE;
+  return TGP_OK;
+}
+
+int vm_for(int V) { return V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16; }
+
+int64_t grad_work_bytes(const tgp_pop* pop, const tgp_data* d) {
+  (void)pop;
+  (void)d;
+  return 0;
+}
+
+// Fill unset fields of a launch configuration.
+tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_out, bool grad) {
+  tgp_cfg c{};
+  if (in) c = *in;
+  if (!in || c.mode == TGP_MODE_AUTO) {
+    tgp_cfg cached{};
+    if (autotune_lookup(pop, d, n_out, grad, &cached)) {
+      const int flags = c.flags;
+      c = cached;
+      c.flags |= flags;
+    }
+  }
+  if ((c.points_per_lane != 4 && c.points_per_lane != 8) || d->V > 8) c.points_per_lane = d->V > 8 ? 4 : 8;
+  const int64_t tile = 64LL * c.points_per_lane;
+  const int64_t ntiles = (d->D + tile - 1) / tile;
+  if (c.mode < TGP_MODE_TREE_MAJOR || c.mode > TGP_MODE_PERSISTENT)
+    c.mode = d->D > 16384 ? TGP_MODE_POINT_MAJOR : TGP_MODE_TREE_MAJOR;
+  if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4)
+    c.block_waves = (int)std::min<int64_t>(4, std::max<int64_t>(1, ntiles));
+  if (c.trees_per_unit < 1) {
+    if (c.mode == TGP_MODE_POINT_MAJOR) {
+      const int64_t ngroups = (ntiles + c.block_waves - 1) / c.block_waves;
+      c.trees_per_unit = (int)std::max<int64_t>(1, (pop->P * ngroups + 8191) / 8192);
+    } else {
+      c.trees_per_unit = 8;
+    }
+  }
+  return c;
+}
+
+int device_cus() {
+  static int cus = -1;
+  static std::mutex m;
+  std::lock_guard<std::mutex> g(m);
+  if (cus < 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+      cus = p.multiProcessorCount;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Enqueue prep + plan (+ order). Returns the plan-related pointers.
+tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
+                        const Layout& L, int32_t* out_info, int32_t* out_status, bool want_order,
+                        hipStream_t s) {
+  int32_t* counters = (int32_t*)(ws + L.counters);
+  if (launch_prep(counters, kCounters, s) != hipSuccess) return TGP_E_HIP;
+  PlanArgs pa{};
+  pa.type = pop->type;
+  pa.value = pop->value;
+  pa.size = pop->size;
+  pa.P = pop->P;
+  pa.Lmax = pop->Lmax;
+  pa.row_stride = pop->row_stride;
+  pa.V = V;
+  pa.n_out = n_out;
+  pa.check_tail = (c.flags & TGP_FLAG_NO_TAIL_CHECK) ? 0 : 1;
+  pa.info = (int32_t*)(ws + L.info);
+  pa.prog = (uint2*)(ws + L.prog);
+  pa.pstride = prog_stride(pop->Lmax);
+  pa.acc = (double*)(ws + L.acc);
+  pa.hist = counters;
+  pa.out_info = out_info;
+  pa.out_status = out_status;
+  if (launch_plan(pa, s) != hipSuccess) return TGP_E_HIP;
+  if (want_order) {
+    OrderArgs oa{};
+    oa.info = pa.info;
+    oa.P = pop->P;
+    oa.hist = counters;
+    oa.cursor = counters + 16;
+    oa.order = (int32_t*)(ws + L.order);
+    if (launch_order(oa, s) != hipSuccess) return TGP_E_HIP;
+  }
+  return TGP_OK;
+}
+
+tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, int n_out, float* mse,
+                   float* pred, int64_t ldp, int32_t* tree_status, void* ws, size_t ws_bytes,
+                   hipStream_t s) {
+  tgp_status st = check_pop(pop);
+  if (st) return st;
+  st = check_data(d, mse != nullptr);
+  if (st) return st;
+  if (pred && ldp < d->D) return TGP_E_SHAPE;
+  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, d));
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  if (pop->P == 0) return TGP_OK;
+  const tgp_cfg c = resolve(cfg, pop, d, n_out, false);
+  char* w = (char*)ws;
+  st = enqueue_plan(pop, d->V, n_out, c, w, L, nullptr, nullptr, c.mode == TGP_MODE_PERSISTENT, s);
+  if (st) return st;
+
+  const int K = c.points_per_lane;
+  const int64_t tile = 64LL * K;
+  const int64_t ntiles = (d->D + tile - 1) / tile;
+  const int bw = c.block_waves;
+  EvalArgs ea{};
+  ea.X = d->X;
+  ea.ldx = d->ldx;
+  ea.V = d->V;
+  ea.D = d->D;
+  ea.Y = mse ? d->Y : nullptr;
+  ea.ldy = d->ldy;
+  ea.n_out = n_out;
+  ea.info = (const int32_t*)(w + L.info);
+  ea.prog = (const uint2*)(w + L.prog);
+  ea.pstride = prog_stride(pop->Lmax);
+  ea.acc = (double*)(w + L.acc);
+  ea.pred = pred;
+  ea.ldp = ldp;
+  ea.P = pop->P;
+  ea.order = (const int32_t*)(w + L.order);
+  ea.mode = c.mode;
+  ea.ntiles = (int32_t)ntiles;
+  ea.ngroups = (int32_t)((ntiles + bw - 1) / bw);
+  ea.tpu = c.mode == TGP_MODE_TREE_MAJOR ? 1 : c.trees_per_unit;
+  ea.queue = (int32_t*)(w + L.counters) + 48;
+  int64_t grid;
+  if (c.mode == TGP_MODE_TREE_MAJOR) {
+    grid = pop->P * ea.ngroups;
+  } else if (c.mode == TGP_MODE_POINT_MAJOR) {
+    grid = ((pop->P + ea.tpu - 1) / ea.tpu) * ea.ngroups;
+  } else {
+    ea.n_units = ((pop->P + ea.tpu - 1) / ea.tpu) * ntiles;
+    const int64_t waves = (int64_t)device_cus() * 12;  // resident waves the kernel can hold
+    grid = std::max<int64_t>(1, std::min<int64_t>((ea.n_units + bw - 1) / bw, waves / bw));
+  }
+  const int NO = (n_out > 1) ? kMaxOut : 1;
+  void* tok = nullptr;
+  profile_before(s, &tok);
+  const hipError_t le = launch_eval(ea, K, vm_for(d->V), NO, pred != nullptr, bw, grid, s);
+  profile_after(s, tok);
+  if (le != hipSuccess) return TGP_E_HIP;
+  FinalArgs fa{};
+  fa.info = ea.info;
+  fa.acc = ea.acc;
+  fa.P = pop->P;
+  fa.inv_D = 1.0 / (double)d->D;
+  fa.mse = mse;
+  fa.tree_status = tree_status;
+  if ((mse || tree_status) && launch_finalize(fa, s) != hipSuccess) return TGP_E_HIP;
+  return TGP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) size_t tgp_workspace_bytes(const tgp_pop* pop, const tgp_data* data,
+                                                                   int32_t n_out, int32_t want_grad) {
+  if (check_pop(pop) != TGP_OK) return 0;
+  if (data && check_data(data, false) != TGP_OK) return 0;
+  if (n_out < 1 || n_out > kMaxOut) return 0;
+  int64_t gb = 0;
+  if (want_grad && data) gb = grad_work_bytes(pop, data);
+  return layout(pop->P, pop->Lmax, gb).total;
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_plan(const tgp_pop* pop, int32_t V, int32_t n_out,
+                                                           const tgp_cfg* cfg, int32_t* info,
+                                                           int32_t* tree_status, void* ws, size_t ws_bytes,
+                                                           hipStream_t stream) {
+  tgp_status st = check_pop(pop);
+  if (st) return st;
+  if (V < 1 || n_out < 1) return TGP_E_SHAPE;
+  if (V > kMaxV || n_out > kMaxOut) return TGP_E_UNSUPPORTED;
+  const Layout L = layout(pop->P, pop->Lmax, 0);
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  if (pop->P == 0) return TGP_OK;
+  tgp_cfg c{};
+  if (cfg) c = *cfg;
+  return enqueue_plan(pop, V, n_out, c, (char*)ws, L, info, tree_status, false, stream);
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_eval_mse(const tgp_pop* pop, const tgp_data* data,
+                                                               const tgp_cfg* cfg, float* mse,
+                                                               int32_t* tree_status, void* ws,
+                                                               size_t ws_bytes, hipStream_t stream) {
+  if (!mse) return TGP_E_ARG;
+  if (!data) return TGP_E_ARG;
+  if (data->n_out != 1) return TGP_E_SHAPE;
+  return forward(pop, data, cfg, 1, mse, nullptr, 0, tree_status, ws, ws_bytes, stream);
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_eval_multi_output(
+    const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg, float* mse, float* pred, int64_t ldp,
+    int32_t* tree_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!mse && !pred) return TGP_E_ARG;
+  if (!data) return TGP_E_ARG;
+  return forward(pop, data, cfg, data->n_out, mse, pred, ldp, tree_status, ws, ws_bytes, stream);
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
+    const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg, const float* grad_mse, float* mse,
+    float* grad_value, float* grad_X, int32_t* tree_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)pop; (void)data; (void)cfg; (void)grad_mse; (void)mse; (void)grad_value; (void)grad_X;
+  (void)tree_status; (void)ws; (void)ws_bytes; (void)stream;
+  return TGP_E_UNSUPPORTED;
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data,
+                                                               int32_t n_out, int32_t want_grad, tgp_cfg* out,
+                                                               void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)want_grad;
+  if (!out) return TGP_E_ARG;
+  tgp_status st = check_pop(pop);
+  if (st) return st;
+  st = check_data(data, true);
+  if (st) return st;
+  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, data));
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  return autotune_run(pop, data, n_out, out, ws, ws_bytes, stream);
+}
+
+__attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) {
+  switch (s) {
+    case TGP_OK: return "ok";
+    case TGP_E_ARG: return "invalid argument (null pointer or bad scalar)";
+    case TGP_E_SHAPE: return "inconsistent sizes or strides";
+    case TGP_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case TGP_E_UNSUPPORTED: return "unsupported size (Lmax > 1024, V > 16 or n_out > 4)";
+    case TGP_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"
+
+// forward entry used by the autotuner (same checks as the public calls)
+tgp_status tgp_internal_forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, int n_out, float* mse,
+                                void* ws, size_t ws_bytes, hipStream_t s) {
+  return forward(pop, d, cfg, n_out, mse, nullptr, 0, nullptr, ws, ws_bytes, s);
+}

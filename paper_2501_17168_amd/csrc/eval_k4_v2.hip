@@ -1,0 +1,6 @@
+// Instantiation of the forward-evaluation kernels for K = 4 points per lane, up to 2 input variables.
+#include "eval_impl.h"
+
+namespace tgp {
+template hipError_t launch_eval_kv<4, 2>(const EvalArgs&, int, bool, int, int64_t, hipStream_t);
+}  // namespace tgp

@@ -1,0 +1,82 @@
+// Internal instruction set of the wave-uniform tree interpreter.
+//
+// The plan kernel compiles every valid tree into a short program for an
+// accumulator machine; the evaluation kernels run it with one wave per
+// (tree, point tile), every lane holding K data points. Registers per lane:
+//   A      accumulator (K values)
+//   T      second-operand register (K)
+//   R0..R3 spill slots in registers (K each); slots 4..7 live in LDS ("RM")
+//   X0..   the tile of input variables (K per variable)
+//   r      Modi contribution register (K), O[o] output accumulators (K each)
+// A program evaluates the tree bottom-up in post-order, taking the child
+// that needs more spill slots first (Sethi-Ullman order), so a tree of at
+// most 1024 nodes never needs more than 8 slots. Leaves are not
+// instructions of their own: they are source operands of their parent.
+//
+// Each instruction is 8 bytes: word = case | aux << 16, then a float
+// payload (the constant of a C source). aux holds an LDS slot (0..7) or a
+// Modi output index.
+#pragma once
+#include <stdint.h>
+
+namespace tgp {
+
+// ---- node encoding (tensor level) ----
+constexpr int kTypeVar = 0, kTypeConst = 1, kTypeFunc = 2, kTypeModi0 = 3;
+constexpr int kOpAdd = 0, kOpSub = 1, kOpMul = 2, kOpDiv = 3, kOpSin = 4, kOpCos = 5, kOpTanh = 6,
+              kOpExp = 7, kOpLog = 8, kOpMax = 9, kOpMin = 10, kOpTan = 11, kNumOps = 12;
+__host__ __device__ constexpr int op_arity(int op) {
+  return (op == kOpAdd || op == kOpSub || op == kOpMul || op == kOpDiv || op == kOpMax || op == kOpMin) ? 2 : 1;
+}
+// index among binary ops (add sub mul div max min) and unary ops (sin cos tanh exp log tan)
+__host__ __device__ constexpr int bin_index(int op) { return op <= kOpDiv ? op : op - 5; }
+__host__ __device__ constexpr int un_index(int op) { return op == kOpTan ? 5 : op - 4; }
+
+constexpr float kDivTau = 1e-6f;   // protected division threshold
+constexpr float kLogEps = 1e-6f;   // protected log offset
+constexpr float kExpClamp = 20.0f; // exp argument clamp
+
+// ---- limits ----
+constexpr int kMaxLmax = 1024;
+constexpr int kMaxV = 16;
+constexpr int kMaxOut = 4;
+constexpr int kRegSlots = 4;       // spill slots held in registers
+constexpr int kMaxSlots = 8;       // spill slots in total (need <= 8 for len <= 1024)
+
+// ---- source operands ----
+// s in [0,16): X[s]; 16: constant payload; 17..20: R0..R3; 21: LDS slot in aux
+constexpr int kSrcX0 = 0, kSrcC = 16, kSrcR0 = 17, kSrcRM = 21, kNumSrc = 22;
+
+// ---- cases ----
+constexpr int kLD = 0;                    // A = src
+constexpr int kTLD = kLD + kNumSrc;       // T = src
+constexpr int kADD = kTLD + kNumSrc;      // A = A + src
+constexpr int kMUL = kADD + kNumSrc;      // A = A * src
+constexpr int kMAX = kMUL + kNumSrc;      // A = max(A, src)
+constexpr int kMIN = kMAX + kNumSrc;      // A = min(A, src)
+constexpr int kSUBA = kMIN + kNumSrc;     // A = A - src
+constexpr int kSUBR = kSUBA + kNumSrc;    // A = src - A
+constexpr int kSPL = kSUBR + kNumSrc;     // R[k] = A, k < 4
+constexpr int kSPLM = kSPL + kRegSlots;   // LDS slot aux = A
+constexpr int kTA = kSPLM + 1;            // T = A
+constexpr int kBT = kTA + 1;              // A = op(A,T) (ord 0) or op(T,A) (ord 1): kBT + 2*bin_index + ord
+constexpr int kUN = kBT + 12;             // A = f(A): kUN + un_index
+constexpr int kMB = kUN + 6;              // r = op(A,T)|op(T,A); A = second operand's value
+constexpr int kMU = kMB + 12;             // r = f(A)
+constexpr int kACC = kMU + 6;             // O[aux] += r
+constexpr int kEND = kACC + 1;
+constexpr int kNumCases = kEND + 1;
+
+__host__ __device__ constexpr uint32_t mkword(int c, int aux = 0) {
+  return (uint32_t)c | ((uint32_t)aux << 16);
+}
+
+// ---- per-tree plan record (int32 fields) ----
+// info[t*kInfoStride + k]
+constexpr int kInfoStatus = 0, kInfoLen = 1, kInfoMaxStack = 2, kInfoNConst = 3, kInfoNModi = 4,
+              kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoStride = 8;
+
+// program capacity per tree, in instructions (bound: 2*len + #unary nodes + 2 <= 3*Lmax + 2)
+__host__ __device__ constexpr int64_t prog_stride(int Lmax) { return ((3 * (int64_t)Lmax + 2) + 7) / 8 * 8; }
+
+}  // namespace tgp

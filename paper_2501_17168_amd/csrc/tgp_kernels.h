@@ -1,0 +1,83 @@
+// Kernel argument blocks and launch helpers shared by the library's HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tgp.h"
+#include "tgp_isa.h"
+
+namespace tgp {
+
+struct PlanArgs {
+  const float* type;
+  const float* value;
+  const float* size;
+  int64_t P;
+  int32_t Lmax;
+  int64_t row_stride;
+  int32_t V;
+  int32_t n_out;
+  int32_t check_tail;
+  int32_t* info;        // [P][kInfoStride]
+  uint2* prog;          // [P][prog_stride(Lmax)]
+  int64_t pstride;
+  double* acc;          // [P], zeroed by the plan
+  int32_t* hist;        // [16] length-bucket histogram (may be null)
+  int32_t* out_info;    // optional [P][6]
+  int32_t* out_status;  // optional [P]
+};
+
+struct OrderArgs {
+  const int32_t* info;
+  int64_t P;
+  const int32_t* hist;  // [16]
+  int32_t* cursor;      // [17], zero on entry (16 buckets + invalid trees)
+  int32_t* order;       // [P] tree indices, longest length bucket first
+};
+
+struct EvalArgs {
+  const float* X;
+  int64_t ldx;
+  int32_t V;
+  int64_t D;
+  const float* Y;       // null in prediction-only mode
+  int64_t ldy;
+  int32_t n_out;
+  const int32_t* info;
+  const uint2* prog;
+  int64_t pstride;
+  double* acc;          // [P]
+  float* pred;          // optional [P][n_out][ldp]
+  int64_t ldp;
+  int64_t P;
+  const int32_t* order; // optional tree order (persistent mode)
+  int32_t mode;         // 1 tree-major, 2 point-major, 3 persistent
+  int32_t ntiles;       // point tiles of 64*K points
+  int32_t ngroups;      // tile groups of block_waves tiles (tree-major / point-major)
+  int32_t tpu;          // trees per unit
+  int64_t n_units;      // persistent: number of (tree chunk, tile) units
+  int32_t* queue;       // persistent: unit counter, zero on entry
+};
+
+struct FinalArgs {
+  const int32_t* info;
+  const double* acc;
+  int64_t P;
+  double inv_D;
+  float* mse;
+  int32_t* tree_status;
+};
+
+// launchers (defined in plan.hip / eval.hip)
+hipError_t launch_prep(int32_t* counters, int n, hipStream_t s);
+hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
+hipError_t launch_order(const OrderArgs& a, hipStream_t s);
+hipError_t launch_eval(const EvalArgs& a, int K, int VM, int NO, bool pred, int block_waves,
+                       int64_t grid, hipStream_t s);
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+
+// optional event pair around the evaluation kernel (measure.hip)
+void profile_before(hipStream_t s, void** token);
+void profile_after(hipStream_t s, void* token);
+
+}  // namespace tgp

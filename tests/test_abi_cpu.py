@@ -1,0 +1,114 @@
+"""The C-ABI library on the host: it loads, exports every declared symbol, and
+rejects bad arguments synchronously before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2501_17168_amd as tgp
+from paper_2501_17168_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # never dereferenced: every call below fails a host check first
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "tgp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tgp_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = tgp.load()
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def pop(P=10, Lmax=64, stride=None):
+    return _lib.TgpPop(FAKE, FAKE, FAKE, P, Lmax, Lmax if stride is None else stride)
+
+
+def data(V=2, D=100, ldx=None, Y=FAKE, n_out=1, ldy=None):
+    return _lib.TgpData(FAKE, V, D, D if ldx is None else ldx, Y, n_out, D if ldy is None else ldy)
+
+
+def ws_bytes(p, d, n_out=1, grad=0):
+    return tgp.load().tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d) if d else None, n_out, grad)
+
+
+def test_workspace_bytes():
+    small = ws_bytes(pop(10, 64), data())
+    big = ws_bytes(pop(1000, 64), data())
+    assert small > 0 and big > small
+    assert ws_bytes(pop(10, 1025), data()) == 0          # Lmax beyond 1024
+    assert ws_bytes(pop(10, 64), data(V=17)) == 0
+    assert ws_bytes(pop(10, 64), data(), n_out=5) == 0
+    assert ws_bytes(pop(10, 64, stride=32), data()) == 0
+    # program store: (3 Lmax + 2) instructions of 8 bytes per tree dominates
+    assert ws_bytes(pop(1000, 1024), data()) >= 1000 * (3 * 1024 + 2) * 8
+
+
+def call_mse(p, d, ws=FAKE * 16, nbytes=1 << 40, mse=FAKE):
+    lib = tgp.load()
+    return lib.tgp_eval_mse(ctypes.byref(p) if p else None, ctypes.byref(d) if d else None, None,
+                            ctypes.c_void_p(mse) if mse else None, None, ctypes.c_void_p(ws) if ws else None,
+                            nbytes, None)
+
+
+def test_eval_mse_host_checks():
+    assert call_mse(None, data()) == _lib.TGP_E_ARG
+    assert call_mse(pop(), None) == _lib.TGP_E_ARG
+    assert call_mse(pop(), data(), mse=0) == _lib.TGP_E_ARG
+    assert call_mse(pop(), data(Y=0)) == _lib.TGP_E_ARG
+    assert call_mse(pop(Lmax=0), data()) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(Lmax=2048), data()) == _lib.TGP_E_UNSUPPORTED
+    assert call_mse(pop(stride=10), data()) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(P=-1), data()) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(V=0)) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(V=17)) == _lib.TGP_E_UNSUPPORTED
+    assert call_mse(pop(), data(D=0)) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(ldx=50)) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(ldy=50)) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(n_out=2)) == _lib.TGP_E_SHAPE
+    assert call_mse(pop(), data(), ws=0) == _lib.TGP_E_WORKSPACE
+    assert call_mse(pop(), data(), ws=FAKE * 16 + 8) == _lib.TGP_E_WORKSPACE   # misaligned
+    assert call_mse(pop(), data(), nbytes=64) == _lib.TGP_E_WORKSPACE
+    # an empty population is a no-op, nothing is launched
+    assert call_mse(pop(P=0), data()) == _lib.TGP_OK
+
+
+def test_multi_output_and_plan_host_checks():
+    lib = tgp.load()
+    p, d = pop(), data(n_out=3)
+    r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d), None, None, None, 0, None,
+                                  ctypes.c_void_p(FAKE * 16), 1 << 40, None)
+    assert r == _lib.TGP_E_ARG                              # neither mse nor pred
+    r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d), None, None, ctypes.c_void_p(FAKE), 10, None,
+                                  ctypes.c_void_p(FAKE * 16), 1 << 40, None)
+    assert r == _lib.TGP_E_SHAPE                            # ldp < D
+    d5 = data(n_out=5)
+    r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d5), None, ctypes.c_void_p(FAKE), None, 0, None,
+                                  ctypes.c_void_p(FAKE * 16), 1 << 40, None)
+    assert r == _lib.TGP_E_UNSUPPORTED
+    assert lib.tgp_plan(ctypes.byref(p), 0, 1, None, None, None, ctypes.c_void_p(FAKE * 16), 1 << 40,
+                        None) == _lib.TGP_E_SHAPE
+    assert lib.tgp_plan(ctypes.byref(p), 2, 1, None, None, None, None, 1 << 40, None) == _lib.TGP_E_WORKSPACE
+    out = _lib.TgpCfg()
+    assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d), 1, 0, None, None, 0, None) == _lib.TGP_E_ARG
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -4, -5, -6, 7):
+        s = tgp.status_str(code)
+        assert isinstance(s, str) and s
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libtgp.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
