@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--workload", default="hybrid", choices=["plain", "hybrid", "dataparallel", "batched", "grad"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--save-cfg", default=None, help="write the chosen launch configuration (JSON) here")
-    ap.add_argument("--load-cfg", default=None, help="use this launch configuration (JSON) instead of tuning")
+    ap.add_argument("--load-cfg", default=None, help="use this launch configuration (JSON file) instead of tuning")
+    ap.add_argument("--cfg", default=None, help="use this launch configuration (JSON text) instead of tuning")
+    ap.add_argument("--no-roofline", action="store_true", help="skip the operator-cost measurement (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -109,7 +111,9 @@ def main():
     gpops_per_step = float(sum_len) * w.D
 
     cfg = None
-    if args.load_cfg:
+    if args.cfg:
+        cfg = json.loads(args.cfg)
+    elif args.load_cfg:
         with open(args.load_cfg) as f:
             cfg = json.load(f)
     elif not args.no_autotune:
@@ -147,7 +151,10 @@ def main():
     value = gpops_per_step * args.steps / (ms * 1e-3)
 
     # ---- roofline of the evaluation kernel ----
-    costs, add_rate = op_costs(tgp)
+    if args.no_roofline:
+        costs, add_rate = [float("nan")] * len(OP_NAMES), float("nan")
+    else:
+        costs, add_rate = op_costs(tgp)
     t = w.type
     fn = t >= 2
     ops = w.value[fn].astype(np.int64)

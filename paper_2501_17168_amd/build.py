@@ -19,7 +19,10 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtgp.so")
 ARCH = "gfx950"
 
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics",
+                # keep the wave-uniform dispatch switch a plain scalar branch tree (no structurized
+                # flow blocks that copy the whole register state around it)
+                "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 

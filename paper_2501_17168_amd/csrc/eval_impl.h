@@ -32,7 +32,7 @@ namespace {
 constexpr int kWave = 64;
 
 template <int K>
-constexpr int kLdsFloatsPerWave = (kMaxSlots - kRegSlots + 1) * K * kWave;
+constexpr int kLdsFloatsPerWave = (kMaxSlots - kRegSlots) * K * kWave;
 
 template <int K, int VM, int NO>
 struct Regs {
@@ -66,24 +66,13 @@ __device__ __forceinline__ float un_op(float a) {
   else return tanf(a);
 }
 
-__device__ __forceinline__ float apply_un(int u, float a) {
-  switch (u) {
-    case 0: return un_op<0>(a);
-    case 1: return un_op<1>(a);
-    case 2: return un_op<2>(a);
-    case 3: return un_op<3>(a);
-    case 4: return un_op<4>(a);
-    default: return un_op<5>(a);
-  }
-}
-
 // value of source S for point slot j
 template <int S, int K, int VM, int NO>
-__device__ __forceinline__ float src_val(const Regs<K, VM, NO>& s, int j, float cv, const float* rm) {
-  if constexpr (S < kSrcC) return s.X[S < VM ? S : 0][j];
-  else if constexpr (S == kSrcC) return cv;
+__device__ __forceinline__ float src_val(const Regs<K, VM, NO>& s, int j, float cv, const float* spill, int aux) {
+  if constexpr (S == kSrcC) return cv;
   else if constexpr (S < kSrcRM) return s.R[S - kSrcR0][j];
-  else return rm[j * kWave];
+  else if constexpr (S == kSrcRM) return spill[((aux & (kMaxSlots - 1)) - kRegSlots) * (K * kWave) + j * kWave];
+  else return s.X[(S - kSrcX0) < VM ? (S - kSrcX0) : 0][j];
 }
 
 template <int K, int VM, int NO>
@@ -99,30 +88,37 @@ __device__ __forceinline__ void add_out(Regs<K, VM, NO>& s, int o) {
   }
 }
 
+// program words live in device memory that no kernel writes while it is
+// being interpreted; the constant address space lets the compiler read them
+// with scalar loads
+typedef const __attribute__((address_space(4))) unsigned long long* prog_ptr;
+
 // Interpret one program on this lane's K points. `spill` points at this
-// wave's LDS spill area [kMaxSlots - kRegSlots][K][64] and `ubuf` at its
-// staging row [K][64], both offset by the lane.
+// wave's LDS spill area [kMaxSlots - kRegSlots][K][64], offset by the lane.
+// The next instruction word is fetched while the current one executes; the
+// empty asm statements pin where the compiler waits for that scalar load
+// (at the end of the iteration, not right after issuing it).
 template <int K, int VM, int NO>
-__device__ __forceinline__ void run_program(const uint2* __restrict__ prog, int prog_len, Regs<K, VM, NO>& s,
-                                            float* spill, float* ubuf) {
-  uint2 ins = prog[0];
-  int pc = 1;
-  // The program ends with END; the trip count bound only guarantees that a
-  // malformed program can neither run away nor read past its slot.
-  for (; pc <= prog_len;) {
-    const uint32_t w = ins.x;
-    const float cv = __uint_as_float(ins.y);
-    ins = prog[pc];
-    ++pc;
+__device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, float* spill) {
+  unsigned long long ins = prog[0];
+  asm volatile("" : "+s"(ins));
+  // one exit (after the latch), so the loop is a single-entry single-exit
+  // region made only of uniform branches
+  bool done = false;
+  for (;;) {
+    ++prog;
+    const unsigned long long nxt = prog[0];
+    const uint32_t w = (uint32_t)ins;
+    const float cv = __uint_as_float((uint32_t)(ins >> 32));
     const int c = (int)(w & 0xffffu);
     const int aux = (int)(w >> 16);
-    const float* rm = spill + ((aux & (kMaxSlots - 1)) - kRegSlots) * (K * kWave);
+    int un = -1;
 
 #define TGP_SRC_CASE(BASE, S, STMT)                                   \
   case (BASE) + (S): {                                                \
-    if constexpr ((S) >= kSrcC || (S) < VM) {                         \
+    if constexpr ((S) < kSrcX0 || (S) - kSrcX0 < VM) {                \
       _Pragma("unroll") for (int j = 0; j < K; ++j) {                 \
-        const float v = src_val<(S), K, VM, NO>(s, j, cv, rm);        \
+        const float v = src_val<(S), K, VM, NO>(s, j, cv, spill, aux); \
         STMT;                                                         \
       }                                                               \
     }                                                                 \
@@ -154,17 +150,18 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ prog, int 
     _Pragma("unroll") for (int j = 0; j < K; ++j) s.r[j] = bin_op<(B)>(s.T[j], s.A[j]);     \
     break;
 
+// Unary (transcendental) cases only record which function to apply: the
+// library implementations branch per lane, and keeping those divergent
+// branches out of the dispatch switch keeps the switch a purely scalar
+// branch tree (no per-lane flow merges that copy the register state).
 #define TGP_UN_CASE(U)     \
   case kUN + (U):          \
     un = (U);              \
     break;                 \
   case kMU + (U):          \
-    un = (U);              \
-    un_to_r = true;        \
+    un = (U) | 8;          \
     break;
 
-    int un = -1;
-    bool un_to_r = false;
     switch (c) {
       TGP_SRC_CASES(kLD, s.A[j] = v)
       TGP_SRC_CASES(kTLD, s.T[j] = v)
@@ -214,9 +211,8 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ prog, int 
       case kACC:
         add_out<K, VM, NO>(s, aux);
         break;
-      case kEND:
-        return;
-      default:
+      default:  // kEND (or any word that is not an instruction)
+        done = true;
         break;
     }
 #undef TGP_SRC_CASE
@@ -224,20 +220,45 @@ __device__ __forceinline__ void run_program(const uint2* __restrict__ prog, int 
 #undef TGP_BT_CASE
 #undef TGP_UN_CASE
     if (un >= 0) {
-      // One shared copy of the transcendental code: stage A through LDS and
-      // loop over the K points (code size, not arithmetic, is the constraint).
+      float t[K];
+      switch (un & 7) {
+        case 0:
 #pragma unroll
-      for (int j = 0; j < K; ++j) ubuf[j * kWave] = s.A[j];
-#pragma nounroll
-      for (int j = 0; j < K; ++j) ubuf[j * kWave] = apply_un(un, ubuf[j * kWave]);
-      if (un_to_r) {
+          for (int j = 0; j < K; ++j) t[j] = un_op<0>(s.A[j]);
+          break;
+        case 1:
 #pragma unroll
-        for (int j = 0; j < K; ++j) s.r[j] = ubuf[j * kWave];
+          for (int j = 0; j < K; ++j) t[j] = un_op<1>(s.A[j]);
+          break;
+        case 2:
+#pragma unroll
+          for (int j = 0; j < K; ++j) t[j] = un_op<2>(s.A[j]);
+          break;
+        case 3:
+#pragma unroll
+          for (int j = 0; j < K; ++j) t[j] = un_op<3>(s.A[j]);
+          break;
+        case 4:
+#pragma unroll
+          for (int j = 0; j < K; ++j) t[j] = un_op<4>(s.A[j]);
+          break;
+        default:
+#pragma unroll
+          for (int j = 0; j < K; ++j) t[j] = un_op<5>(s.A[j]);
+          break;
+      }
+      if (un & 8) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) s.r[j] = t[j];
       } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) s.A[j] = ubuf[j * kWave];
+        for (int j = 0; j < K; ++j) s.A[j] = t[j];
       }
     }
+    unsigned long long n2 = nxt;
+    asm volatile("" : "+s"(n2));
+    ins = n2;
+    if (done) break;
   }
 }
 
@@ -266,8 +287,8 @@ __device__ __forceinline__ void load_x(const EvalArgs& a, Regs<K, VM, NO>& s, in
 
 // Evaluate tree t on the tile whose first point for this lane is p0.
 template <int K, int VM, int NO, bool PRED>
-__device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, float* spill, float* ubuf,
-                                          int64_t t, int64_t p0, int lane) {
+__device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, float* spill, int64_t t,
+                                          int64_t p0, int lane) {
   const int32_t* inf = a.info + t * kInfoStride;
   const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
   if (status != 0) {
@@ -290,8 +311,7 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
     for (int j = 0; j < K; ++j) s.O[q][j] = 0.0f;
 #pragma unroll
   for (int j = 0; j < K; ++j) s.A[j] = 0.0f;
-  const int prog_len = __builtin_amdgcn_readfirstlane(inf[kInfoProgLen]);
-  run_program<K, VM, NO>(a.prog + t * a.pstride, prog_len, s, spill, ubuf);
+  run_program<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), s, spill);
   // outputs: a tree without Modi nodes predicts (root, 0, ..., 0)
   if (nmodi == 0) {
 #pragma unroll
@@ -333,13 +353,12 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
 
 template <int K, int VM, int NO, bool PRED>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
-  // per wave: LDS spill slots 4..7 and the transcendental staging row
+  // per wave: LDS spill slots 4..7
   extern __shared__ float s_lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int W = blockDim.x / kWave;
   float* spill = s_lds + wv * (kLdsFloatsPerWave<K>) + lane;
-  float* ubuf = spill + (kMaxSlots - kRegSlots) * K * kWave;
   Regs<K, VM, NO> s;
   constexpr int kTile = K * kWave;
   const bool persistent = a.mode == TGP_MODE_PERSISTENT;
@@ -374,7 +393,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
     for (int64_t k = t0; k < t1; ++k) {
       const int64_t t = persistent ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[k]) : k;
       if (t < 0 || t >= a.P) continue;
-      eval_tree<K, VM, NO, PRED>(a, s, spill, ubuf, t, p0, lane);
+      eval_tree<K, VM, NO, PRED>(a, s, spill, t, p0, lane);
     }
   }
 }

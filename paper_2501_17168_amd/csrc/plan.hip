@@ -378,7 +378,10 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         put(prog, a.pstride, pos + 1, mkword(kBT + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
       }
     }
-    if (lane == 0) put(prog, a.pstride, prog_len - 1, mkword(kEND), 0.0f);
+    if (lane == 0) {
+      put(prog, a.pstride, prog_len - 1, mkword(kEND), 0.0f);
+      put(prog, a.pstride, prog_len, mkword(kEND), 0.0f);  // read by the interpreter's one-word lookahead
+    }
   }
 
   if (status != 0) {

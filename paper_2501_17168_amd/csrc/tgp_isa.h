@@ -15,7 +15,8 @@
 //
 // Each instruction is 8 bytes: word = case | aux << 16, then a float
 // payload (the constant of a C source). aux holds an LDS slot (0..7) or a
-// Modi output index.
+// Modi output index. Programs are straight-line and end with END, so the
+// interpreter's program counter only moves forward and always reaches END.
 #pragma once
 #include <stdint.h>
 
@@ -44,8 +45,10 @@ constexpr int kRegSlots = 4;       // spill slots held in registers
 constexpr int kMaxSlots = 8;       // spill slots in total (need <= 8 for len <= 1024)
 
 // ---- source operands ----
-// s in [0,16): X[s]; 16: constant payload; 17..20: R0..R3; 21: LDS slot in aux
-constexpr int kSrcX0 = 0, kSrcC = 16, kSrcR0 = 17, kSrcRM = 21, kNumSrc = 22;
+// 0: constant payload; 1..4: R0..R3; 5: LDS slot in aux; 6..21: X0..X15
+// (variables last, so the cases a kernel instantiated for fewer variables
+// cannot reach form one contiguous range per group)
+constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 
 // ---- cases ----
 constexpr int kLD = 0;                    // A = src
