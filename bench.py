@@ -11,7 +11,12 @@ shape, already in device memory when the timed region starts.
 
 Prints one JSON line. Extra objects:
   roofline      the evaluation kernel against the vector-ALU issue peak;
-  cpu_baseline  the CPU oracle timed on the host (a baseline, not a target).
+  cpu_baseline  the CPU oracle timed on the host (a baseline, not a target);
+  forms         the same workload through the plain forward kernel (one tree
+                per workgroup, fixed shape), the batched persistent queue
+                replayed as a captured hipGraph, and forward + adjoint
+                (fitness, d/d constants and d/dX), each in GPops/s and as a
+                ratio to the plain forward kernel.
 """
 
 import argparse
@@ -30,7 +35,7 @@ METRIC = "GPops/s (tree nodes × points / s), fwd MSE and fwd+adjoint vs plain f
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "tanh", "exp", "log", "max", "min", "tan")
 HELPER = {7: 1.0, 11: 1.0}   # the exp and tan micro-kernels carry one extra sub / mul per step
-EVAL_SOURCES = ("eval_impl.h", "tgp_isa.h", "tgp_kernels.h")
+EVAL_SOURCES = ("eval_impl.h", "interp.h", "tgp_isa.h", "tgp_kernels.h")
 
 
 def parse():
@@ -46,6 +51,9 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true", help="skip the operator-cost measurement (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the plain-forward / batched-persistent graph / forward+adjoint comparison")
+    ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
     return ap.parse_args()
 
 
@@ -77,6 +85,68 @@ def op_costs(tgp):
     rates = [_lib.op_rate(o) for o in range(len(OP_NAMES))]
     base = rates[0]
     return [max(1.0, base / r - HELPER.get(o, 0.0)) for o, r in enumerate(rates)], base
+
+
+def timed_ms(torch, fn, steps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
+    """Plain forward vs batched persistent (hipGraph replay) vs forward + adjoint on one workload."""
+    res = {}
+    plain = tgp.cfg(mode=1, points_per_lane=4, block_waves=4)
+    ws = tgp.Workspace(X.device)
+    out = torch.empty(w.P, dtype=torch.float32, device=X.device)
+
+    def fwd(c):
+        if w.n_out == 1:
+            tgp.eval_mse(pop, X, Y, config=c, ws=ws, out=out)
+        else:
+            tgp.eval_multi_output(pop, X, Y, config=c, ws=ws, out=out)
+
+    ms_plain = timed_ms(torch, lambda: fwd(plain), steps)
+    res["plain_fwd"] = {"cfg": "tree-major, 4 points/lane, 4 waves/workgroup", "ms": ms_plain,
+                        "GPops/s": gpops_per_step / (ms_plain * 1e-3)}
+
+    if not tuned:
+        tuned = tgp.autotune(pop, X, Y, n_out=w.n_out)
+    pers_d = {"mode": 3, "points_per_lane": tuned.get("points_per_lane", 4),
+              "trees_per_unit": tuned.get("trees_per_unit", 4) if tuned.get("mode") == 3 else 4,
+              "block_waves": tuned.get("block_waves", 4), "flags": 0}
+    pers = tgp.cfg(pers_d)
+    fwd(pers)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fwd(pers)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fwd(pers)
+    ms_graph = timed_ms(torch, g.replay, steps)
+    res["batched_persistent_graph"] = {"cfg": pers_d, "ms": ms_graph, "GPops/s": gpops_per_step / (ms_graph * 1e-3),
+                                       "vs_plain_fwd": ms_plain / ms_graph}
+    del g
+
+    if w.n_out == 1:
+        def fwd_adj():
+            tgp.eval_mse_grad(pop, X, Y, ws=ws)
+
+        ms_adj = timed_ms(torch, fwd_adj, steps)
+        res["fwd_adjoint"] = {"outputs": "fitness, d/d constants, d/dX", "ms": ms_adj,
+                              "GPops/s": gpops_per_step / (ms_adj * 1e-3), "vs_plain_fwd": ms_plain / ms_adj}
+    return res
 
 
 def main():
@@ -150,6 +220,8 @@ def main():
     ms_step = ms / args.steps
     value = gpops_per_step * args.steps / (ms * 1e-3)
 
+    forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
+
     # ---- roofline of the evaluation kernel ----
     if args.no_roofline:
         costs, add_rate = [float("nan")] * len(OP_NAMES), float("nan")
@@ -196,7 +268,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
                       "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
-           "roofline": roofline, "cpu_baseline": cpu}
+           "roofline": roofline, "cpu_baseline": cpu, "forms": forms}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -452,7 +452,7 @@ def predict(pop_type, pop_value, pop_size, X, n_out=1, rows=None):
 
 
 # ---------------------------------------------------------------- gradients
-def grad_tree(d, X, Y, n_out, g=1.0):
+def grad_tree(d, X, Y, n_out, g=1.0, shadow=False):
     """Reverse-mode gradient of g * fitness for one tree, with a full tape.
 
     Returns (mse, grad_value [len], grad_X [V][D]). grad_value is non-zero
@@ -460,8 +460,16 @@ def grad_tree(d, X, Y, n_out, g=1.0):
     function node passes adj * df/dchild to each child; a Modi node for
     output o passes (output adjoint of o) * df/dchild to each child and also
     its own parent adjoint to its rightmost child (the value it hands up).
+
+    shadow=True is the float32 shadow of the same sweep: node values come
+    from the float32 shadow operators, and the residual, the output adjoint,
+    each partial derivative, each product and each adjoint sum are rounded
+    to float32 (the per-constant sums over points stay float64). It only
+    classifies gradient components as well- or ill-conditioned.
     """
-    X = np.asarray(X, np.float64)
+    q = _r32 if shadow else (lambda v: v)
+    op_val = apply_op_shadow32 if shadow else apply_op
+    X = q(np.asarray(X, np.float64))
     V, D = X.shape
     n = d.length
     val = [None] * n
@@ -469,16 +477,16 @@ def grad_tree(d, X, Y, n_out, g=1.0):
     stack = []
     for i in range(n - 1, -1, -1):
         if d.kind[i] != T_FUNC:
-            val[i] = _leaf(d, i, X, D)
+            val[i] = q(_leaf(d, i, X, D))
             stack.append(val[i])
             continue
         op = d.arg[i]
         if OPS[op][1] == 2:
             a = stack.pop(); b = stack.pop()
-            r = apply_op(op, a, b); right = b
+            r = op_val(op, a, b); right = b
         else:
             a = stack.pop()
-            r = apply_op(op, a); right = a
+            r = op_val(op, a); right = a
         if d.out[i] >= 0:
             contrib[i] = (d.out[i], r)
             val[i] = right
@@ -486,11 +494,11 @@ def grad_tree(d, X, Y, n_out, g=1.0):
             val[i] = r
         stack.append(val[i])
     out = _outputs(d, stack[0], contrib, n_out, D)
-    Yd = _Y(Y, n_out, D)
+    Yd = q(_Y(Y, n_out, D))
     with np.errstate(all="ignore"):
-        resid = out - Yd
+        resid = q(q(out) - Yd)
         m = float(np.sum(resid * resid) / D)
-        gout = g * 2.0 * resid / D
+        gout = q(q(q(g * 2.0) * resid) * q(1.0 / D)) if shadow else g * 2.0 * resid / D
     adj = [np.zeros(D) for _ in range(n)]
     if d.n_modi == 0:
         adj[0] = gout[0].copy()
@@ -509,26 +517,27 @@ def grad_tree(d, X, Y, n_out, g=1.0):
             kids = [c1] if OPS[op][1] == 1 else [c1, c1 + d.size[c1]]
             if len(kids) == 2:
                 da, db = op_partials(op, val[kids[0]], val[kids[1]])
-                parts = [da, db]
+                parts = [q(da), q(db)]
             else:
                 da, _ = op_partials(op, val[kids[0]])
-                parts = [da]
+                parts = [q(da)]
             if d.out[i] >= 0:
                 go = gout[d.out[i]]
                 for c, p in zip(kids, parts):
-                    adj[c] = adj[c] + go * p
-                adj[kids[-1]] = adj[kids[-1]] + adj[i]
+                    adj[c] = q(adj[c] + q(go * p))
+                adj[kids[-1]] = q(adj[kids[-1]] + adj[i])
             else:
                 for c, p in zip(kids, parts):
-                    adj[c] = adj[c] + adj[i] * p
+                    adj[c] = q(adj[c] + q(adj[i] * p))
     return m, gv, gX
 
 
-def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None):
+def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, shadow=False):
     """Gradients of sum_t g_t * fitness_t.
 
     Returns (mse [R], grad_value [R][Lmax] (zero off constant nodes, zero for
-    invalid trees), grad_X [V][D] summed over the listed trees)."""
+    invalid trees), grad_X [V][D] summed over the listed trees). shadow=True
+    gives the float32 shadow of the same gradients (see grad_tree)."""
     X = np.asarray(X, np.float64)
     V, D = X.shape
     rows = list(range(pop_type.shape[0]) if rows is None else rows)
@@ -541,7 +550,7 @@ def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None):
         if d.status != OK:
             continue
         gt = 1.0 if g is None else float(g[p])
-        m[k], gvt, gXt = grad_tree(d, X, Y, n_out, gt)
+        m[k], gvt, gXt = grad_tree(d, X, Y, n_out, gt, shadow=shadow)
         gv[k, :d.length] = gvt
         gX += gXt
     return m, gv, gX

@@ -13,4 +13,5 @@ from ._lib import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_multi_output, eval_mse_grad, autotune,
+    TreeMSE,
 )

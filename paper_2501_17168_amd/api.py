@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import TgpCfg, TgpData, TgpPop, check
 
 __all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output",
-           "eval_mse_grad", "autotune"]
+           "eval_mse_grad", "autotune", "TreeMSE"]
 
 
 def _dev(t, name, dtype=torch.float32):
@@ -173,7 +173,7 @@ def eval_mse(pop, X, y, config=None, ws=None, out=None, tree_status=None, stream
 
 
 def eval_multi_output(pop, X, Y=None, n_out=None, want_mse=True, want_pred=False, config=None, ws=None,
-                      tree_status=None, stream=None):
+                      tree_status=None, stream=None, out=None):
     """Multi-output evaluation. Returns (mse [P] or None, pred [P][n_out][D] or None)."""
     lib = _lib.load()
     if Y is None:
@@ -182,7 +182,7 @@ def eval_multi_output(pop, X, Y=None, n_out=None, want_mse=True, want_pred=False
     n_out = d.n_out
     p = pop.abi()
     D = X.shape[1]
-    mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device) if want_mse else None
+    mse = (torch.empty((pop.P,), dtype=torch.float32, device=X.device) if out is None else out) if want_mse else None
     pred = torch.empty((pop.P, n_out, D), dtype=torch.float32, device=X.device) if want_pred else None
     nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), n_out, 0)
     if nbytes == 0:
@@ -240,3 +240,31 @@ def autotune(pop, X, Y, n_out=None, want_grad=False, ws=None, stream=None):
     check(lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d), d.n_out, int(bool(want_grad)), ctypes.byref(out),
                            wp, wn, _stream(stream)), "tgp_autotune")
     return out.as_dict()
+
+
+class TreeMSE(torch.autograd.Function):
+    """Fitness of every tree as a differentiable function of the node values and X.
+
+    ``TreeMSE.apply(value, type, size, X, y)`` returns float32 [P]. Backward calls
+    tgp_eval_mse_grad with the incoming gradient as the per-tree weights and
+    returns (grad_value, None, None, grad_X, None). grad_value is zero at
+    every non-constant and padding position, so an optimizer step on ``value``
+    moves only the constants (a zero gradient gives Adam a zero step, and NaN
+    padding stays NaN)."""
+
+    @staticmethod
+    def forward(ctx, value, type, size, X, y):
+        pop = Population(type, value, size)
+        mse = eval_mse(pop, X, y)
+        ctx.save_for_backward(value, type, size, X, y)
+        return mse
+
+    @staticmethod
+    def backward(ctx, grad_mse):
+        value, type, size, X, y = ctx.saved_tensors
+        pop = Population(type, value, size)
+        want_v = ctx.needs_input_grad[0]
+        want_x = ctx.needs_input_grad[3]
+        _, gv, gx = eval_mse_grad(pop, X, y, grad_mse=grad_mse.contiguous().float(), want_grad_value=want_v,
+                                  want_grad_x=want_x)
+        return gv, None, None, gx, None

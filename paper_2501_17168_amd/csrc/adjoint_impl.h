@@ -1,0 +1,297 @@
+#pragma once
+// Fitness gradient by a reverse sweep over each tree, with recomputation.
+//
+// L = sum_t g_t * mse_t. For every (tree, point tile) a wave
+//   1. runs the tree's forward program once: output, residual e, the
+//      fitness contribution and the output adjoint gbar = g_t * 2 e / D;
+//   2. walks the tree's adjoint records (one per function node, pre-order
+//      with the smaller child first). A record takes its adjoint either
+//      from the previous record or from the pending stack, recomputes the
+//      values of its function children by re-running their code ranges of
+//      the forward program (their code is contiguous), forms the partial
+//      derivatives and hands each child its adjoint: a variable leaf adds it
+//      to the lane's grad_X accumulator, a constant leaf adds the wave's sum
+//      to grad_value, a function child becomes the next record's adjoint or
+//      waits on the pending stack (at most log2(len) entries deep).
+// Nothing is stored per point beyond the current path's adjoints. A Modi
+// node (single output) hands gbar * df/dchild to its children and passes its
+// own adjoint on to its rightmost child, whose value it forwards.
+//
+// Work units are point-major: each workgroup holds block_waves tiles and a
+// run of trees, so grad_X accumulates in registers across the run and is
+// written with one float atomic per (lane, point, variable) at the end.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "interp.h"
+#include "tgp_kernels.h"
+
+namespace tgp {
+
+namespace {
+
+using namespace interp;
+
+typedef const __attribute__((address_space(4))) uint32_t* rec_ptr;
+
+// partial derivatives of op at (a, b); b unused for unary ops
+__device__ __forceinline__ void partials(int op, float a, float b, float& da, float& db) {
+  da = 1.0f;
+  db = 0.0f;
+  switch (op) {
+    case kOpAdd: db = 1.0f; break;
+    case kOpSub: db = -1.0f; break;
+    case kOpMul: da = b; db = a; break;
+    case kOpDiv: {
+      const bool small = fabsf(b) < kDivTau;
+      const float r = 1.0f / b;
+      da = small ? 0.0f : r;
+      db = small ? 0.0f : -a * r * r;
+    } break;
+    case kOpMax: {
+      const bool pa = (a >= b) || isnan(b);
+      da = pa ? 1.0f : 0.0f;
+      db = pa ? 0.0f : 1.0f;
+    } break;
+    case kOpMin: {
+      const bool pa = (a <= b) || isnan(b);
+      da = pa ? 1.0f : 0.0f;
+      db = pa ? 0.0f : 1.0f;
+    } break;
+    case kOpSin: da = cosf(a); break;
+    case kOpCos: da = -sinf(a); break;
+    case kOpTanh: {
+      const float th = tanhf(a);
+      da = 1.0f - th * th;
+    } break;
+    case kOpExp: da = (a >= -kExpClamp && a <= kExpClamp) ? expf(a) : 0.0f; break;
+    case kOpLog: da = a == 0.0f ? 0.0f : copysignf(1.0f, a) / (fabsf(a) + kLogEps); break;
+    default: {  // tan
+      const float tn = tanf(a);
+      da = 1.0f + tn * tn;
+    } break;
+  }
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <int K, int VM>
+struct AdjState {
+  Regs<K, VM, 1> s;
+  float gx[VM][K];  // grad_X accumulators for this lane's points
+};
+
+template <int K, int VM>
+__device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, 1>& s, int64_t p0) {
+#pragma unroll
+  for (int v = 0; v < VM; ++v) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = p0 + j * kWave;
+      s.X[v][j] = (v < a.V && p < a.D) ? a.X[(int64_t)v * a.ldx + p] : 0.0f;
+    }
+  }
+}
+
+// value of a child for this lane's K points: variable, constant or recomputed subtree
+template <int K, int VM>
+__device__ __forceinline__ void child_value(Regs<K, VM, 1>& s, float* spill, prog_ptr prog, int kind, int var,
+                                            uint32_t w1, uint32_t w2, float out[K]) {
+  if (kind == kKindFunc) {
+    run_program<K, VM, 1, true>(prog + w1, s, spill, (int)w2);
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] = s.A[j];
+  } else if (kind == kKindConst) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] = __uint_as_float(w2);
+  } else {
+#pragma unroll
+    for (int v = 0; v < VM; ++v)
+      if (v == var) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) out[j] = s.X[v][j];
+      }
+  }
+}
+
+// a leaf child receives its adjoint
+template <int K, int VM>
+__device__ __forceinline__ void leaf_adjoint(const AdjArgs& a, AdjState<K, VM>& st, int64_t t, int64_t p0,
+                                             int lane, int kind, int var, uint32_t node, const float adj[K]) {
+  if (kind == kKindVar) {
+#pragma unroll
+    for (int v = 0; v < VM; ++v)
+      if (v == var) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) st.gx[v][j] += adj[j];
+      }
+  } else if (kind == kKindConst && a.grad_value) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) sum += (p0 + j * kWave < a.D) ? adj[j] : 0.0f;
+    sum = wave_sum_f32(sum);
+    if (lane == 0) atomicAdd(&a.grad_value[t * a.gv_stride + node], sum);
+  }
+}
+
+}  // namespace
+
+template <int K, int VM>
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
+  extern __shared__ float s_lds[];
+  constexpr int kTile = K * kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int W = blockDim.x / kWave;
+  const int per_wave = (kMaxSlots - kRegSlots + a.pend_slots) * K * kWave;
+  float* spill = s_lds + wv * per_wave + lane;
+  float* pend = spill + (kMaxSlots - kRegSlots) * K * kWave;
+
+  const int64_t b = blockIdx.x;
+  const int g = (int)(b % a.ngroups);
+  const int tile = g * W + wv;
+  if (tile >= a.ntiles) return;
+  const int64_t t0 = (b / a.ngroups) * a.tpu;
+  const int64_t t1 = min(a.P, t0 + a.tpu);
+  const int64_t p0 = (int64_t)tile * kTile + lane;
+
+  AdjState<K, VM> st;
+  Regs<K, VM, 1>& s = st.s;
+  load_x_adj<K, VM>(a, s, p0);
+#pragma unroll
+  for (int v = 0; v < VM; ++v)
+#pragma unroll
+    for (int j = 0; j < K; ++j) st.gx[v][j] = 0.0f;
+
+  for (int64_t t = t0; t < t1; ++t) {
+    const int32_t* inf = a.info + t * kInfoStride;
+    const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
+    if (status != 0) continue;
+    const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
+    const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
+    const float gt = a.grad_mse ? a.grad_mse[t] : 1.0f;
+    prog_ptr prog = (prog_ptr)(a.prog + t * a.pstride);
+
+    // ---- forward: output, fitness, output adjoint ----
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      s.A[j] = 0.0f;
+      s.O[0][j] = 0.0f;
+    }
+    run_program<K, VM, 1, false>(prog, s, spill);
+    float gbar[K];
+    double sse = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = p0 + j * kWave;
+      const float out = nmodi ? s.O[0][j] : s.A[j];
+      gbar[j] = 0.0f;
+      if (p < a.D) {
+        const float e = out - a.Y[p];
+        sse += (double)(e * e);
+        gbar[j] = gt * 2.0f * e * a.inv_D;
+      }
+    }
+    sse = wave_sum_f64(sse);
+    if (lane == 0) unsafeAtomicAdd(&a.acc[t], sse);
+
+    // ---- reverse sweep over the adjoint records ----
+    if (nint == 0) {  // the tree is a single leaf
+      const uint2 ins = a.prog[t * a.pstride];
+      const int src = (int)(ins.x & 0xffffu) - kLD;
+      if (src >= kSrcX0)
+        leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
+      else
+        leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
+      continue;
+    }
+    rec_ptr recs = (rec_ptr)(a.adj + t * (int64_t)a.Lmax * kAdjWords);
+    float cur[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+    int sp = 0;
+    for (int q = 0; q < nint; ++q) {
+      const uint32_t w0 = recs[kAdjWords * q], w1 = recs[kAdjWords * q + 1], w2 = recs[kAdjWords * q + 2];
+      const uint32_t w3 = recs[kAdjWords * q + 3], w4 = recs[kAdjWords * q + 4];
+      const int op = w0 & 15, ar = (w0 >> 4) & 3, modi = (w0 >> 6) & 1, c2first = (w0 >> 7) & 1;
+      const int pop = (w0 >> 8) & 1, push = (w0 >> 9) & 1;
+      const int k1 = (w0 >> 10) & 3, k2 = (w0 >> 12) & 3, v1 = (w0 >> 14) & 15, v2 = (w0 >> 18) & 15;
+      float adj[K];
+      if (pop) {
+        sp = sp > 0 ? sp - 1 : 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) adj[j] = pend[(sp * K + j) * kWave];
+      } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) adj[j] = cur[j];
+      }
+      // children values (not needed for add / sub)
+      float va[K], vb[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) va[j] = vb[j] = 0.0f;
+      if (op != kOpAdd && op != kOpSub) {
+        child_value<K, VM>(s, spill, prog, k1, v1, w1, w2, va);
+        if (ar == 2) child_value<K, VM>(s, spill, prog, k2, v2, w3, w4, vb);
+      }
+      float a1[K], a2[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        float da, db;
+        partials(op, va[j], vb[j], da, db);
+        const float base = modi ? gbar[j] : adj[j];
+        a1[j] = base * da;
+        a2[j] = base * db;
+        if (modi) {  // the handed-up value is the rightmost child's
+          if (ar == 2) a2[j] += adj[j];
+          else a1[j] += adj[j];
+        }
+      }
+      // leaves take their adjoint now; function children go on
+      if (k1 != kKindFunc) leaf_adjoint<K, VM>(a, st, t, p0, lane, k1, v1, w1, a1);
+      if (ar == 2 && k2 != kKindFunc) leaf_adjoint<K, VM>(a, st, t, p0, lane, k2, v2, w3, a2);
+      if (push) {  // both children are function nodes
+        const float* second = c2first ? a1 : a2;
+        const float* first = c2first ? a2 : a1;
+        if (sp < a.pend_slots) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) pend[(sp * K + j) * kWave] = second[j];
+          ++sp;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = first[j];
+      } else if (k1 == kKindFunc) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = a1[j];
+      } else if (ar == 2 && k2 == kKindFunc) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = a2[j];
+      }
+    }
+  }
+
+  // ---- grad_X: one atomic per (lane, point, variable) for the whole run ----
+  if (a.grad_X) {
+#pragma unroll
+    for (int v = 0; v < VM; ++v) {
+      if (v < a.V) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int64_t p = p0 + j * kWave;
+          if (p < a.D) atomicAdd(&a.grad_X[(int64_t)v * a.ldx + p], st.gx[v][j]);
+        }
+      }
+    }
+  }
+}
+
+template <int K, int VM>
+hipError_t launch_adjoint_kv(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s) {
+  const size_t lds = (size_t)block_waves * (kMaxSlots - kRegSlots + a.pend_slots) * K * kWave * sizeof(float);
+  adjoint_kernel<K, VM><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace tgp

@@ -75,10 +75,16 @@ tgp_status check_ws(void* ws, size_t ws_bytes, size_t need) {
 
 int vm_for(int V) { return V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16; }
 
+// adjoint records: one 32-byte record per function node, Lmax slots per tree
 int64_t grad_work_bytes(const tgp_pop* pop, const tgp_data* d) {
-  (void)pop;
   (void)d;
-  return 0;
+  return (int64_t)pop->P * pop->Lmax * kAdjWords * (int64_t)sizeof(uint32_t);
+}
+
+int pend_slots_for(int Lmax) {
+  int lg = 0;
+  while ((1 << (lg + 1)) <= Lmax) ++lg;
+  return lg + 2;
 }
 
 // Fill unset fields of a launch configuration.
@@ -129,7 +135,7 @@ int device_cus() {
 // Enqueue prep + plan (+ order). Returns the plan-related pointers.
 tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
                         const Layout& L, int32_t* out_info, int32_t* out_status, bool want_order,
-                        hipStream_t s) {
+                        hipStream_t s, bool want_adj = false) {
   int32_t* counters = (int32_t*)(ws + L.counters);
   if (launch_prep(counters, kCounters, s) != hipSuccess) return TGP_E_HIP;
   PlanArgs pa{};
@@ -146,6 +152,7 @@ tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, 
   pa.prog = (uint2*)(ws + L.prog);
   pa.pstride = prog_stride(pop->Lmax);
   pa.acc = (double*)(ws + L.acc);
+  pa.adj = want_adj ? (uint32_t*)(ws + L.gwork) : nullptr;
   pa.hist = counters;
   pa.out_info = out_info;
   pa.out_status = out_status;
@@ -170,7 +177,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   st = check_data(d, mse != nullptr);
   if (st) return st;
   if (pred && ldp < d->D) return TGP_E_SHAPE;
-  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, d));
+  const Layout L = layout(pop->P, pop->Lmax, 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   if (pop->P == 0) return TGP_OK;
@@ -283,21 +290,82 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_multi_output(
 __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
     const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg, const float* grad_mse, float* mse,
     float* grad_value, float* grad_X, int32_t* tree_status, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)pop; (void)data; (void)cfg; (void)grad_mse; (void)mse; (void)grad_value; (void)grad_X;
-  (void)tree_status; (void)ws; (void)ws_bytes; (void)stream;
-  return TGP_E_UNSUPPORTED;
+  if (!mse) return TGP_E_ARG;
+  tgp_status st = check_pop(pop);
+  if (st) return st;
+  st = check_data(data, true);
+  if (st) return st;
+  if (data->n_out != 1) return TGP_E_SHAPE;
+  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, data));
+  st = check_ws(ws, ws_bytes, L.total);
+  if (st) return st;
+  if (pop->P == 0) return TGP_OK;
+  tgp_cfg c{};
+  if (cfg) c = *cfg;
+  c.mode = TGP_MODE_POINT_MAJOR;
+  c.points_per_lane = 4;
+  if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 4;
+  char* w = (char*)ws;
+  st = enqueue_plan(pop, data->V, 1, c, w, L, nullptr, nullptr, false, stream, true);
+  if (st) return st;
+  if (launch_zero_f32(grad_value, pop->P, pop->row_stride, pop->row_stride, stream) != hipSuccess) return TGP_E_HIP;
+  if (launch_zero_f32(grad_X, data->V, data->D, data->ldx, stream) != hipSuccess) return TGP_E_HIP;
+
+  const int K = 4;
+  const int bw = c.block_waves;
+  const int64_t tile = 64LL * K;
+  const int64_t ntiles = (data->D + tile - 1) / tile;
+  const int64_t ngroups = (ntiles + bw - 1) / bw;
+  int64_t tpu = c.trees_per_unit;
+  if (tpu < 1) tpu = std::max<int64_t>(1, (pop->P * ngroups + 2047) / 2048);
+  AdjArgs aa{};
+  aa.X = data->X;
+  aa.ldx = data->ldx;
+  aa.V = data->V;
+  aa.D = data->D;
+  aa.Y = data->Y;
+  aa.inv_D = (float)(1.0 / (double)data->D);
+  aa.info = (const int32_t*)(w + L.info);
+  aa.prog = (const uint2*)(w + L.prog);
+  aa.pstride = prog_stride(pop->Lmax);
+  aa.adj = (const uint32_t*)(w + L.gwork);
+  aa.Lmax = pop->Lmax;
+  aa.acc = (double*)(w + L.acc);
+  aa.grad_mse = grad_mse;
+  aa.grad_value = grad_value;
+  aa.gv_stride = pop->row_stride;
+  aa.grad_X = grad_X;
+  aa.P = pop->P;
+  aa.ntiles = (int32_t)ntiles;
+  aa.ngroups = (int32_t)ngroups;
+  aa.tpu = (int32_t)tpu;
+  aa.pend_slots = pend_slots_for(pop->Lmax);
+  const int64_t grid = ((pop->P + tpu - 1) / tpu) * ngroups;
+  void* tok = nullptr;
+  profile_before(stream, &tok);
+  const hipError_t le = launch_adjoint(aa, K, vm_for(data->V), bw, grid, stream);
+  profile_after(stream, tok);
+  if (le != hipSuccess) return TGP_E_HIP;
+  FinalArgs fa{};
+  fa.info = aa.info;
+  fa.acc = aa.acc;
+  fa.P = pop->P;
+  fa.inv_D = 1.0 / (double)data->D;
+  fa.mse = mse;
+  fa.tree_status = tree_status;
+  if (launch_finalize(fa, stream) != hipSuccess) return TGP_E_HIP;
+  return TGP_OK;
 }
 
 __attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data,
                                                                int32_t n_out, int32_t want_grad, tgp_cfg* out,
                                                                void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)want_grad;
   if (!out) return TGP_E_ARG;
   tgp_status st = check_pop(pop);
   if (st) return st;
   st = check_data(data, true);
   if (st) return st;
-  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, data));
+  const Layout L = layout(pop->P, pop->Lmax, want_grad ? grad_work_bytes(pop, data) : 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   return autotune_run(pop, data, n_out, out, ws, ws_bytes, stream);

@@ -60,10 +60,10 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // source operand of a leaf for instruction encoding
-__device__ __forceinline__ void leaf_src(int r, const float* __restrict__ vrow, int i, int& src, float& pay) {
+__device__ __forceinline__ void leaf_src(int r, const float* vals, int i, int& src, float& pay) {
   if (rec_kind(r) == kTypeConst) {
     src = kSrcC;
-    pay = vrow[i];
+    pay = vals[i];
   } else {
     src = kSrcX0 + rec_var(r);
     pay = 0.0f;
@@ -95,11 +95,24 @@ __device__ __forceinline__ int fused_case(int op, bool a_first, int src) {
 
 }  // namespace
 
+constexpr int kMaxChunks = kMaxLmax / kWave;
+
+// LDS per tree: rec, need|code size, start|base, constant value, adjoint
+// order (int/float, Lpad each) and subtree size (short, Lpad); Lpad = Lmax
+// rounded up to 64.
+__host__ __device__ constexpr size_t plan_lds_bytes(int Lmax) {
+  return (size_t)((Lmax + kWave - 1) / kWave * kWave) * (5 * sizeof(int) + sizeof(short));
+}
+
 __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
-  __shared__ int s_rec[kMaxLmax];
-  __shared__ short s_sz[kMaxLmax];
-  __shared__ int s_nc[kMaxLmax];  // need << 16 | code size; -1 = unknown
-  __shared__ int s_sb[kMaxLmax];  // start | base << 16; -1 = unknown
+  extern __shared__ int s_plan[];
+  const int Lpad = (a.Lmax + kWave - 1) / kWave * kWave;
+  int* s_rec = s_plan;
+  int* s_nc = s_rec + Lpad;  // need << 16 | code size; -1 = unknown
+  int* s_sb = s_nc + Lpad;   // start | base << 16; -1 = unknown
+  float* s_val = (float*)(s_sb + Lpad);
+  int* s_ai = (int*)(s_val + Lpad);  // internal-node count, then record position | pop << 16
+  short* s_sz = (short*)(s_ai + Lpad);
 
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
@@ -111,49 +124,81 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   uint2* prog = a.prog + t * a.pstride;
   const int Lmax = a.Lmax;
 
+  // Issue every global load of the row at once (the padding check reads all
+  // Lmax entries, so their count is known before len is).
+  float tv[kMaxChunks], vv[kMaxChunks], sv[kMaxChunks];
+  const int nch_all = (Lmax + kWave - 1) / kWave;
+  int nch_loaded = a.check_tail ? nch_all : 0;
+#pragma unroll
+  for (int ch = 0; ch < kMaxChunks; ++ch) {
+    const int i = ch * kWave + lane;
+    tv[ch] = vv[ch] = sv[ch] = __builtin_nanf("");
+    if (ch < nch_loaded && i < Lmax) {
+      tv[ch] = trow[i];
+      vv[ch] = vrow[i];
+      sv[ch] = srow[i];
+    }
+  }
+  const float s0 = a.check_tail ? __shfl(sv[0], 0, kWave) : srow[0];
+
   int status = 0;
   int len = 0;
-  const float s0 = srow[0];
   if (!(is_intf(s0) && s0 >= 1.0f && s0 <= (float)Lmax)) status = 1;
   else len = (int)s0;
 
-  int n_const = 0, n_modi = 0, max_stack = 0, need0 = 0, prog_len = 0;
+  int n_const = 0, n_modi = 0, max_stack = 0, need0 = 0, prog_len = 0, n_int = 0;
 
   if (status == 0) {
+    const int scan_end = a.check_tail ? Lmax : len;
+    if (!a.check_tail) {
+      nch_loaded = (len + kWave - 1) / kWave;
+#pragma unroll
+      for (int ch = 0; ch < kMaxChunks; ++ch) {
+        const int i = ch * kWave + lane;
+        if (ch < nch_loaded && i < len) {
+          tv[ch] = trow[i];
+          vv[ch] = vrow[i];
+          sv[ch] = srow[i];
+        }
+      }
+    }
     // ---- pass 1: decode, NaN / padding / code checks ----
     int err = 1 << 20;
     int size_bad = 0;
-    const int scan_end = a.check_tail ? Lmax : len;
-    for (int base = 0; base < scan_end; base += kWave) {
-      const int i = base + lane;
-      if (i >= scan_end) continue;
-      const float tv = trow[i], vv = vrow[i], sv = srow[i];
+#pragma unroll
+    for (int ch = 0; ch < kMaxChunks; ++ch) {
+      const int i = ch * kWave + lane;
+      if (ch >= nch_loaded || i >= scan_end) continue;
+      const float tq = tv[ch], vq = vv[ch], sq = sv[ch];
       if (i >= len) {
-        if (!(isnan(tv) && isnan(vv) && isnan(sv))) err = min(err, 3);
+        if (!(isnan(tq) && isnan(vq) && isnan(sq))) err = min(err, 3);
         continue;
       }
-      if (isnan(tv) || isnan(vv) || isnan(sv)) {
+      s_nc[i] = 0;
+      s_sb[i] = -1;
+      s_val[i] = vq;
+      if (isnan(tq) || isnan(vq) || isnan(sq)) {
         err = min(err, 2);
         s_rec[i] = 0;
         s_sz[i] = -1;
         continue;
       }
       int rec = 0;
-      if (!(is_intf(tv) && tv >= 0.0f && tv < (float)(kTypeModi0 + a.n_out))) {
+      if (!(is_intf(tq) && tq >= 0.0f && tq < (float)(kTypeModi0 + a.n_out))) {
         err = min(err, 4);
       } else {
-        const int ti = (int)tv;
+        const int ti = (int)tq;
         if (ti == kTypeConst) {
           rec = kTypeConst;
           ++n_const;
         } else if (ti == kTypeVar) {
-          if (!(is_intf(vv) && vv >= 0.0f && vv < (float)a.V)) err = min(err, 6);
-          else rec = kTypeVar | ((int)vv << 12);
+          if (!(is_intf(vq) && vq >= 0.0f && vq < (float)a.V)) err = min(err, 6);
+          else rec = kTypeVar | ((int)vq << 12);
         } else {
-          if (!(is_intf(vv) && vv >= 0.0f && vv < (float)kNumOps)) {
+          if (!(is_intf(vq) && vq >= 0.0f && vq < (float)kNumOps)) {
             err = min(err, 5);
           } else {
-            const int op = (int)vv;
+            const int op = (int)vq;
             const int mo = ti >= kTypeModi0 ? ti - kTypeModi0 : -1;
             rec = kTypeFunc | (op_arity(op) << 2) | (op << 4) | ((mo + 1) << 8);
             if (mo >= 0) ++n_modi;
@@ -161,11 +206,10 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         }
       }
       s_rec[i] = rec;
-      if (is_intf(sv) && sv >= 1.0f && sv <= (float)len) s_sz[i] = (short)(int)sv;
+      if (is_intf(sq) && sq >= 1.0f && sq <= (float)len) s_sz[i] = (short)(int)sq;
       else { s_sz[i] = -1; size_bad = 1; }
       // leaves are complete for the bottom-up pass; function nodes unknown
       s_nc[i] = (rec_kind(rec) == kTypeFunc) ? -1 : 0;
-      s_sb[i] = -1;
     }
     err = wave_min(err);
     n_const = wave_sum(n_const);
@@ -305,7 +349,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     if (rec_kind(root) != kTypeFunc) {
       if (lane == 0) {
         int src; float pay;
-        leaf_src(root, vrow, 0, src, pay);
+        leaf_src(root, s_val, 0, src, pay);
         put(prog, a.pstride, 0, mkword(kLD + src), pay);
       }
     }
@@ -327,7 +371,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (rec_arity(r) == 1) {
         if (l1) {
           int src; float pay;
-          leaf_src(r1, vrow, c1, src, pay);
+          leaf_src(r1, s_val, c1, src, pay);
           put(prog, a.pstride, st, mkword(kLD + src), pay);
         }
         if (mo < 0) {
@@ -346,15 +390,15 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       bool a_first;  // A holds the first operand and src the second
       if (l1 && l2) {
         int s1; float p1;
-        leaf_src(r1, vrow, c1, s1, p1);
+        leaf_src(r1, s_val, c1, s1, p1);
         put(prog, a.pstride, st, mkword(kLD + s1), p1);
-        leaf_src(r2, vrow, c2, src, pay);
+        leaf_src(r2, s_val, c2, src, pay);
         a_first = true;
       } else if (l1) {
-        leaf_src(r1, vrow, c1, src, pay);
+        leaf_src(r1, s_val, c1, src, pay);
         a_first = false;
       } else if (l2) {
-        leaf_src(r2, vrow, c2, src, pay);
+        leaf_src(r2, s_val, c2, src, pay);
         a_first = true;
       } else {
         const int nc1 = s_nc[c1], nc2 = s_nc[c2];
@@ -382,10 +426,116 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       put(prog, a.pstride, prog_len - 1, mkword(kEND), 0.0f);
       put(prog, a.pstride, prog_len, mkword(kEND), 0.0f);  // read by the interpreter's one-word lookahead
     }
+
+    // ---- pass 7: adjoint records (gradient calls only) ----
+    if (a.adj) {
+      // bottom-up: number of function nodes in each subtree
+      for (int base = 0; base < len; base += kWave) {
+        const int i = base + lane;
+        if (i < len) s_ai[i] = rec_kind(s_rec[i]) == kTypeFunc ? -1 : 0;
+      }
+      __syncthreads();
+      for (int ch = nch - 1; ch >= 0; --ch) {
+        const int i = ch * kWave + lane;
+        bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
+        for (int it = 0; it <= kWave; ++it) {
+          if (!done) {
+            const int c1 = i + 1;
+            const int a1 = s_ai[c1];
+            int a2 = 0;
+            if (rec_arity(s_rec[i]) == 2) a2 = s_ai[c1 + s_sz[c1]];
+            if (a1 >= 0 && a2 >= 0) {
+              s_ai[i] = 1 + a1 + a2;
+              done = true;
+            }
+          }
+          __syncthreads();
+          if (__all(done)) break;
+        }
+      }
+      n_int = rec_kind(root) == kTypeFunc ? s_ai[0] : 0;
+      __syncthreads();
+      // top-down: record position and pending flag (smaller child first)
+      if (lane == 0 && rec_kind(root) == kTypeFunc) s_ai[0] = 0 | (1 << 30);
+      __syncthreads();
+      for (int ch = 0; ch < nch; ++ch) {
+        const int i = ch * kWave + lane;
+        bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
+        for (int it = 0; it <= kWave; ++it) {
+          if (!done) {
+            const int qi = s_ai[i];
+            if (qi & (1 << 30)) {
+              const int q = qi & 0xffff;
+              const int c1 = i + 1;
+              const bool f1 = rec_kind(s_rec[c1]) == kTypeFunc;
+              if (rec_arity(s_rec[i]) == 1) {
+                if (f1) s_ai[c1] = (q + 1) | (1 << 30);
+              } else {
+                const int c2 = c1 + s_sz[c1];
+                const bool f2 = rec_kind(s_rec[c2]) == kTypeFunc;
+                const bool c2first = s_sz[c2] < s_sz[c1];
+                const int F = c2first ? c2 : c1, S = c2first ? c1 : c2;
+                const bool fF = c2first ? f2 : f1, fS = c2first ? f1 : f2;
+                const int nF = fF ? s_ai[F] : 0;
+                if (fF) s_ai[F] = (q + 1) | (1 << 30);
+                if (fS) s_ai[S] = (q + 1 + nF) | (1 << 30) | (fF ? (1 << 16) : 0);
+              }
+              done = true;
+            }
+          }
+          __syncthreads();
+          if (__all(done)) break;
+        }
+      }
+      // emission
+      uint32_t* recs = a.adj + t * (int64_t)Lmax * kAdjWords;
+      for (int base = 0; base < len; base += kWave) {
+        const int i = base + lane;
+        if (i >= len) continue;
+        const int r = s_rec[i];
+        if (rec_kind(r) != kTypeFunc) continue;
+        const int qi = s_ai[i];
+        const int q = qi & 0xffff;
+        if (q >= Lmax) continue;
+        const int pop = (qi >> 16) & 1;
+        const int ar = rec_arity(r);
+        const int c1 = i + 1;
+        const int c2 = ar == 2 ? c1 + s_sz[c1] : -1;
+        uint32_t wv[kAdjWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int kinds[2] = {kKindNone, kKindNone}, vars[2] = {0, 0};
+        const int ch2[2] = {c1, c2};
+        bool both_func = ar == 2;
+        for (int k = 0; k < ar; ++k) {
+          const int c = ch2[k];
+          const int rc = s_rec[c];
+          if (rec_kind(rc) == kTypeFunc) {
+            kinds[k] = kKindFunc;
+            wv[1 + 2 * k] = (uint32_t)(s_sb[c] & 0xffff);
+            wv[2 + 2 * k] = (uint32_t)(s_nc[c] & 0xffff);
+          } else if (rec_kind(rc) == kTypeVar) {
+            kinds[k] = kKindVar;
+            vars[k] = rec_var(rc);
+            both_func = false;
+          } else {
+            kinds[k] = kKindConst;
+            wv[1 + 2 * k] = (uint32_t)c;
+            wv[2 + 2 * k] = __float_as_uint(s_val[c]);
+            both_func = false;
+          }
+        }
+        const int c2first = (ar == 2 && s_sz[c2] < s_sz[c1]) ? 1 : 0;
+        wv[0] = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) | (c2first << 7) |
+                           (pop << 8) | ((both_func ? 1 : 0) << 9) | (kinds[0] << 10) | (kinds[1] << 12) |
+                           (vars[0] << 14) | (vars[1] << 18));
+        uint4* dst = (uint4*)(recs + (int64_t)q * kAdjWords);
+        dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        dst[1] = make_uint4(wv[4], 0u, 0u, 0u);
+      }
+    }
   }
 
   if (status != 0) {
-    len = 0; n_const = 0; n_modi = 0; max_stack = 0; need0 = 0; prog_len = 0;
+    len = 0; n_const = 0; n_modi = 0; max_stack = 0; need0 = 0; prog_len = 0; n_int = 0;
   }
   if (lane == 0) {
     const int bucket = len <= 1 ? 0 : 32 - __clz(len - 1);
@@ -397,6 +547,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     info[kInfoBucket] = bucket;
     info[kInfoProgLen] = prog_len;
     info[kInfoNeed] = need0;
+    info[kInfoNInternal] = n_int;
     a.acc[t] = 0.0;
     if (a.hist && status == 0) atomicAdd(&a.hist[bucket], 1);
     if (a.out_status) a.out_status[t] = status;
@@ -439,7 +590,7 @@ hipError_t launch_prep(int32_t* counters, int n, hipStream_t s) {
 
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {
   if (a.P <= 0) return hipSuccess;
-  plan_kernel<<<dim3((unsigned)a.P), dim3(64), 0, s>>>(a);
+  plan_kernel<<<dim3((unsigned)a.P), dim3(64), plan_lds_bytes(a.Lmax), s>>>(a);
   return hipGetLastError();
 }
 

@@ -77,7 +77,26 @@ __host__ __device__ constexpr uint32_t mkword(int c, int aux = 0) {
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]
 constexpr int kInfoStatus = 0, kInfoLen = 1, kInfoMaxStack = 2, kInfoNConst = 3, kInfoNModi = 4,
-              kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoStride = 8;
+              kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoNInternal = 8, kInfoStride = 10;
+
+// ---- adjoint records ----
+// One record (8 x uint32) per function node, in pre-order with the smaller
+// child visited first, so that at most log2(len) adjoints wait on the
+// pending stack. Children are either leaves (a variable or a constant) or
+// function nodes, whose value is recomputed by re-running their contiguous
+// code range [start, start + len) of the forward program.
+//   w0 = op | arity << 4 | modi << 6 | c2_first << 7 | pop << 8 | push << 9
+//        | kind1 << 10 | kind2 << 12 | var1 << 14 | var2 << 18
+//   w1, w2 = child 1: code start, code length (function) or node index,
+//            constant bits (constant)
+//   w3, w4 = child 2, likewise; w5..w7 = 0
+// kind: 0 function, 1 variable, 2 constant, 3 absent (unary node).
+// pop: the node's adjoint comes from the pending stack (it is the second
+// visited function child of its parent); otherwise it is the "current"
+// adjoint left by the previous record. push: the node's second-visited
+// child's adjoint goes to the pending stack.
+constexpr int kAdjWords = 8;
+constexpr int kKindFunc = 0, kKindVar = 1, kKindConst = 2, kKindNone = 3;
 
 // program capacity per tree, in instructions (bound: 2*len + #unary nodes + 2 <= 3*Lmax + 2)
 __host__ __device__ constexpr int64_t prog_stride(int Lmax) { return ((3 * (int64_t)Lmax + 2) + 7) / 8 * 8; }

@@ -22,6 +22,7 @@ struct PlanArgs {
   uint2* prog;          // [P][prog_stride(Lmax)]
   int64_t pstride;
   double* acc;          // [P], zeroed by the plan
+  uint32_t* adj;        // optional [P][Lmax][kAdjWords] adjoint records
   int32_t* hist;        // [16] length-bucket histogram (may be null)
   int32_t* out_info;    // optional [P][6]
   int32_t* out_status;  // optional [P]
@@ -59,6 +60,30 @@ struct EvalArgs {
   int32_t* queue;       // persistent: unit counter, zero on entry
 };
 
+struct AdjArgs {
+  const float* X;
+  int64_t ldx;
+  int32_t V;
+  int64_t D;
+  const float* Y;       // [D]
+  float inv_D;
+  const int32_t* info;
+  const uint2* prog;
+  int64_t pstride;
+  const uint32_t* adj;  // adjoint records [P][Lmax][kAdjWords]
+  int32_t Lmax;
+  double* acc;          // [P]
+  const float* grad_mse;  // optional [P]
+  float* grad_value;    // optional [P][gv_stride], zeroed beforehand
+  int64_t gv_stride;
+  float* grad_X;        // optional [V][ldx], zeroed beforehand
+  int64_t P;
+  int32_t ntiles;
+  int32_t ngroups;
+  int32_t tpu;
+  int32_t pend_slots;   // pending-adjoint stack entries per wave
+};
+
 struct FinalArgs {
   const int32_t* info;
   const double* acc;
@@ -75,6 +100,8 @@ hipError_t launch_order(const OrderArgs& a, hipStream_t s);
 hipError_t launch_eval(const EvalArgs& a, int K, int VM, int NO, bool pred, int block_waves,
                        int64_t grid, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, int K, int VM, int block_waves, int64_t grid, hipStream_t s);
+hipError_t launch_zero_f32(float* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
 
 // optional event pair around the evaluation kernel (measure.hip)
 void profile_before(hipStream_t s, void** token);

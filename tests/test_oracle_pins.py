@@ -364,6 +364,60 @@ def test_modi_gradient_vs_central_differences():
         assert gX[vv_, j] == pytest.approx(f, rel=1e-5, abs=1e-9)
 
 
+def test_gradient_shadow_exact_on_representable_values():
+    # MUL(ADD(x0, 0.5), x1) on small integers: every value, partial and product
+    # is exact in float32, so the float32 shadow equals the float64 sweep.
+    t, v, s = _rows([(2, 2, 5), (2, 0, 3), (0, 0, 1), (1, 0.5, 1), (0, 1, 1)], 8)
+    X = np.array([[1.0, -2.0, 3.0, 0.0], [2.0, 1.0, -1.0, 4.0]])
+    Y = np.array([[1.0, 2.0, -3.0, 0.5]])
+    g64 = O.grad(t[None], v[None], s[None], X, Y)
+    g32 = O.grad(t[None], v[None], s[None], X, Y, shadow=True)
+    for a, b in zip(g64, g32):
+        np.testing.assert_array_equal(a, b)
+    # closed form: d/dc mean((x0 + c) x1 - y)^2 = 2/D sum(((x0 + c) x1 - y) x1)
+    r = (X[0] + 0.5) * X[1] - Y[0]
+    assert g32[1][0, 3] == 2.0 / 4 * np.sum(r * X[1])
+
+
+def test_gradient_shadow_singular_quotient():
+    # COS(DIV(c, x0)) at x0 just above the protection threshold: the quotient is
+    # about 6e5, where one float32 ulp (1/16) moves cos noticeably. The shadow
+    # gradient follows float32 arithmetic written out here; the float64 one
+    # differs, which is what marks such components as ill-conditioned.
+    c, x, y = 1.7, 2.9e-6, 0.25
+    t, v, s = _rows([(2, 5, 4), (2, 3, 3), (1, c, 1), (0, 0, 1)], 8)
+    X = np.array([[x]], dtype=np.float32)
+    Y = np.array([[y]], dtype=np.float32)
+    _, gv32, _ = O.grad(t[None], v[None], s[None], X, Y, shadow=True)
+    _, gv64, _ = O.grad(t[None], v[None], s[None], X, Y)
+    f = np.float32
+    c32, x32 = f(c), f(x)
+    q = f(c32 / x32)
+    e = f(f(np.cos(np.float64(q))) - f(y))
+    gout = f(f(f(2.0) * e) * f(1.0))
+    d_cos = f(-np.sin(np.float64(q)))
+    d_div = f(1.0 / np.float64(x32))
+    want = f(f(gout * d_cos) * d_div)
+    assert gv32[0, 2] == pytest.approx(float(want), rel=1e-6)
+    qe = c32 / np.float64(x32)
+    want64 = 2.0 * (np.cos(qe) - y) * -np.sin(qe) / np.float64(x32)
+    assert gv64[0, 2] == pytest.approx(want64, rel=1e-12)
+    assert abs(gv32[0, 2] - gv64[0, 2]) > 1e-3 * abs(gv64[0, 2])
+
+
+def test_gradient_shadow_close_on_random_trees():
+    # no dropped or misplaced term in the shadow sweep: on a random population
+    # most constant components agree with float64 to 1e-4
+    w = synth.workload("grad", P=200, D=64)
+    Y = w.targets_from(O.predict(*w.hidden, w.X, 1)[:, 0, :])
+    m, gv, _ = O.grad(w.type, w.value, w.size, w.X, Y)
+    _, gs, _ = O.grad(w.type, w.value, w.size, w.X, Y, shadow=True)
+    const = (w.type == O.T_CONST) & np.isfinite(m)[:, None] & np.isfinite(gv) & (np.abs(gv) > 1e-6)
+    close = np.abs(gs - gv) <= 1e-4 * np.abs(gv)
+    assert const.sum() > 100
+    assert close[const].mean() > 0.9
+
+
 def test_adam_reference_matches_torch():
     torch = pytest.importorskip("torch")
     A = np.diag([1.0, 3.0, 0.5])
