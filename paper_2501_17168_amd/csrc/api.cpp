@@ -21,7 +21,7 @@ using namespace tgp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kCounters = 64;  // hist[16] | cursor[17] @16 | queue @48
+constexpr int kCounters = 64 + kMaxQueues * kQueueStride;  // hist[16] | cursor[17] @16 | queues @64
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -153,7 +153,6 @@ tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, 
   pa.pstride = prog_stride(pop->Lmax);
   pa.acc = (double*)(ws + L.acc);
   pa.adj = want_adj ? (uint32_t*)(ws + L.gwork) : nullptr;
-  pa.hist = counters;
   pa.out_info = out_info;
   pa.out_status = out_status;
   if (launch_plan(pa, s) != hipSuccess) return TGP_E_HIP;
@@ -210,7 +209,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   ea.ntiles = (int32_t)ntiles;
   ea.ngroups = (int32_t)((ntiles + bw - 1) / bw);
   ea.tpu = c.mode == TGP_MODE_TREE_MAJOR ? 1 : c.trees_per_unit;
-  ea.queue = (int32_t*)(w + L.counters) + 48;
+  ea.queue = (int32_t*)(w + L.counters) + 64;
   int64_t grid;
   if (c.mode == TGP_MODE_TREE_MAJOR) {
     grid = pop->P * ea.ngroups;
@@ -220,6 +219,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
     ea.n_units = ((pop->P + ea.tpu - 1) / ea.tpu) * ntiles;
     const int64_t waves = (int64_t)device_cus() * 12;  // resident waves the kernel can hold
     grid = std::max<int64_t>(1, std::min<int64_t>((ea.n_units + bw - 1) / bw, waves / bw));
+    ea.nq = (int32_t)std::min<int64_t>(kMaxQueues, grid);
   }
   const int NO = (n_out > 1) ? kMaxOut : 1;
   void* tok = nullptr;

@@ -134,9 +134,12 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
     int tile;
     int64_t t0, t1;
     if (persistent) {
-      int u = 0;
-      if (lane == 0) u = atomicAdd(a.queue, 1);
-      u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, kWave));
+      // queue j hands out units j, j + nq, j + 2 nq, ... in order (longest trees first)
+      const int j = (int)(blockIdx.x % (unsigned)a.nq);
+      int k = 0;
+      if (lane == 0) k = atomicAdd(a.queue + j * kQueueStride, 1);
+      k = __builtin_amdgcn_readfirstlane(__shfl(k, 0, kWave));
+      const int64_t u = (int64_t)j + (int64_t)a.nq * k;
       if (u >= a.n_units) break;
       tile = (int)(u % a.ntiles);
       t0 = (int64_t)(u / a.ntiles) * a.tpu;

@@ -7,12 +7,23 @@
 // the length, the maximum stack depth of the reversed-prefix evaluation of
 // §III-C, the constant and Modi node counts and the length bucket.
 //
-// Code generation runs in three data-parallel passes over the node array
-// held in LDS: a bottom-up pass (spill need and code size of each subtree,
-// iterated to a fixed point within each 64-node chunk, last chunk first),
-// a top-down pass (code start and spill base of each subtree, first chunk
-// first), and an emission pass in which every function node writes its
-// own instructions at positions known from the two passes.
+// Code generation takes the child with the larger subtree first at every
+// node whose two children are both function nodes, and spills its value
+// while the smaller child runs. A value is held only while descending into
+// a subtree of at most half the size, so a tree of at most 1024 nodes needs
+// at most 8 spill slots. With that rule every figure the emitter needs is a
+// sum over a contiguous node range or over the ancestors of a node, and
+// subtrees are contiguous ranges in the prefix encoding (§III-A):
+//   * the code size of a subtree and its count of function nodes are range
+//     sums of per-node contributions (one prefix scan);
+//   * the code start, the spill base and the adjoint-record position of a
+//     node are sums of terms that its ancestors attach to the range of one
+//     of their children (a difference array: each ancestor adds its term at
+//     the first index of the range and subtracts it after the last; one
+//     prefix scan gives, at every node, the sum over its ancestors).
+// Every pass is a fixed number of chunk-wide scans: no per-tree iteration
+// to a fixed point and no dependence on the tree's height.
+
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -31,6 +42,8 @@ __device__ __forceinline__ int rec_arity(int r) { return (r >> 2) & 3; }
 __device__ __forceinline__ int rec_op(int r) { return (r >> 4) & 15; }
 __device__ __forceinline__ int rec_modi(int r) { return ((r >> 8) & 15) - 1; }
 __device__ __forceinline__ int rec_var(int r) { return (r >> 12) & 31; }
+// set on the later-visited child of a node whose children are both function nodes (adjoint order)
+constexpr int kRecPop = 1 << 20;
 
 __device__ __forceinline__ bool is_intf(float x) { return isfinite(x) && x == floorf(x); }
 
@@ -60,10 +73,10 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // source operand of a leaf for instruction encoding
-__device__ __forceinline__ void leaf_src(int r, const float* vals, int i, int& src, float& pay) {
+__device__ __forceinline__ void leaf_src(int r, float value, int& src, float& pay) {
   if (rec_kind(r) == kTypeConst) {
     src = kSrcC;
-    pay = vals[i];
+    pay = value;
   } else {
     src = kSrcX0 + rec_var(r);
     pay = 0.0f;
@@ -95,24 +108,36 @@ __device__ __forceinline__ int fused_case(int op, bool a_first, int src) {
 
 }  // namespace
 
-constexpr int kMaxChunks = kMaxLmax / kWave;
 
-// LDS per tree: rec, need|code size, start|base, constant value, adjoint
-// order (int/float, Lpad each) and subtree size (short, Lpad); Lpad = Lmax
-// rounded up to 64.
+// LDS per tree: node record (int), prefix sums E and difference array D
+// (int, Lmax + 1 entries each, rounded up) and subtree size (short).
+__host__ __device__ constexpr int plan_lpad(int Lmax) { return (Lmax + kWave) / kWave * kWave; }
 __host__ __device__ constexpr size_t plan_lds_bytes(int Lmax) {
-  return (size_t)((Lmax + kWave - 1) / kWave * kWave) * (5 * sizeof(int) + sizeof(short));
+  return (size_t)plan_lpad(Lmax) * (3 * sizeof(int) + sizeof(short));
 }
 
+// packed fields of the prefix sums E: code size (bits 0..15), function nodes (16..31)
+// and of the ancestor sums D: code start (0..11), spill base (12..15), record shift (16..)
+constexpr int kStartBits = 12;
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// NCH = node chunks of 64 held in registers while the row is decoded (Lmax <= 64 NCH)
+template <int NCH>
 __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   extern __shared__ int s_plan[];
-  const int Lpad = (a.Lmax + kWave - 1) / kWave * kWave;
+  const int Lp = plan_lpad(a.Lmax);
   int* s_rec = s_plan;
-  int* s_nc = s_rec + Lpad;  // need << 16 | code size; -1 = unknown
-  int* s_sb = s_nc + Lpad;   // start | base << 16; -1 = unknown
-  float* s_val = (float*)(s_sb + Lpad);
-  int* s_ai = (int*)(s_val + Lpad);  // internal-node count, then record position | pop << 16
-  short* s_sz = (short*)(s_ai + Lpad);
+  int* s_E = s_rec + Lp;  // s_E[i] = sum over nodes < i (code size | function count << 16)
+  int* s_D = s_E + Lp;    // difference array, then ancestor sums (start | base << 12 | shift << 16)
+  short* s_sz = (short*)(s_D + Lp);
 
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
@@ -126,11 +151,11 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
 
   // Issue every global load of the row at once (the padding check reads all
   // Lmax entries, so their count is known before len is).
-  float tv[kMaxChunks], vv[kMaxChunks], sv[kMaxChunks];
+  float tv[NCH], vv[NCH], sv[NCH];
   const int nch_all = (Lmax + kWave - 1) / kWave;
   int nch_loaded = a.check_tail ? nch_all : 0;
 #pragma unroll
-  for (int ch = 0; ch < kMaxChunks; ++ch) {
+  for (int ch = 0; ch < NCH; ++ch) {
     const int i = ch * kWave + lane;
     tv[ch] = vv[ch] = sv[ch] = __builtin_nanf("");
     if (ch < nch_loaded && i < Lmax) {
@@ -153,7 +178,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     if (!a.check_tail) {
       nch_loaded = (len + kWave - 1) / kWave;
 #pragma unroll
-      for (int ch = 0; ch < kMaxChunks; ++ch) {
+      for (int ch = 0; ch < NCH; ++ch) {
         const int i = ch * kWave + lane;
         if (ch < nch_loaded && i < len) {
           tv[ch] = trow[i];
@@ -166,7 +191,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     int err = 1 << 20;
     int size_bad = 0;
 #pragma unroll
-    for (int ch = 0; ch < kMaxChunks; ++ch) {
+    for (int ch = 0; ch < NCH; ++ch) {
       const int i = ch * kWave + lane;
       if (ch >= nch_loaded || i >= scan_end) continue;
       const float tq = tv[ch], vq = vv[ch], sq = sv[ch];
@@ -174,9 +199,6 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         if (!(isnan(tq) && isnan(vq) && isnan(sq))) err = min(err, 3);
         continue;
       }
-      s_nc[i] = 0;
-      s_sb[i] = -1;
-      s_val[i] = vq;
       if (isnan(tq) || isnan(vq) || isnan(sq)) {
         err = min(err, 2);
         s_rec[i] = 0;
@@ -208,8 +230,6 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       s_rec[i] = rec;
       if (is_intf(sq) && sq >= 1.0f && sq <= (float)len) s_sz[i] = (short)(int)sq;
       else { s_sz[i] = -1; size_bad = 1; }
-      // leaves are complete for the bottom-up pass; function nodes unknown
-      s_nc[i] = (rec_kind(rec) == kTypeFunc) ? -1 : 0;
     }
     err = wave_min(err);
     n_const = wave_sum(n_const);
@@ -257,112 +277,119 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     }
     max_stack = wave_max(best);
 
-    // ---- pass 4: bottom-up spill need and code size ----
-    for (int ch = nch - 1; ch >= 0; --ch) {
-      const int i = ch * kWave + lane;
-      bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
-      for (int it = 0; it <= kWave; ++it) {
-        if (!done) {
+    // ---- pass 4: code size and function count of every subtree ----
+    // E[i] = sum over nodes j < i of (code words node j emits | 1 << 16 if j is a function)
+    {
+      int acc = 0;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int i = ch * kWave + lane;
+        int x = 0;
+        if (i < len) {
           const int r = s_rec[i];
-          const int c1 = i + 1;
-          const int nc1 = s_nc[c1];
-          const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
-          const int oc = own_code(r);
-          if (rec_arity(r) == 1) {
-            if (nc1 >= 0) {
-              const int need = l1 ? 0 : (nc1 >> 16);
-              const int cs = (l1 ? 1 : (nc1 & 0xffff)) + oc;
-              s_nc[i] = (need << 16) | cs;
-              done = true;
-            }
-          } else {
-            const int c2 = c1 + s_sz[c1];
-            const int nc2 = s_nc[c2];
-            const bool l2 = rec_kind(s_rec[c2]) != kTypeFunc;
-            if (nc1 >= 0 && nc2 >= 0) {
-              int need, cs;
-              if (l1 && l2) { need = 0; cs = 1 + oc; }
-              else if (l1) { need = nc2 >> 16; cs = (nc2 & 0xffff) + oc; }
-              else if (l2) { need = nc1 >> 16; cs = (nc1 & 0xffff) + oc; }
-              else {
-                const int n1 = nc1 >> 16, n2 = nc2 >> 16;
-                need = (n1 == n2) ? n1 + 1 : max(n1, n2);
-                cs = (nc1 & 0xffff) + (nc2 & 0xffff) + 1 + oc;
-              }
-              s_nc[i] = (need << 16) | cs;
-              done = true;
-            }
-          }
-        }
-        __syncthreads();
-        if (__all(done)) break;
-      }
-    }
-    const int root = s_rec[0];
-    if (rec_kind(root) == kTypeFunc) {
-      need0 = s_nc[0] >> 16;
-      prog_len = (s_nc[0] & 0xffff) + 1;
-    } else {
-      need0 = 0;
-      prog_len = 2;
-    }
-
-    // ---- pass 5: top-down code start and spill base ----
-    if (lane == 0) s_sb[0] = 0;
-    __syncthreads();
-    for (int ch = 0; ch < nch; ++ch) {
-      const int i = ch * kWave + lane;
-      bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
-      for (int it = 0; it <= kWave; ++it) {
-        if (!done) {
-          const int sb = s_sb[i];
-          if (sb >= 0) {
-            const int st = sb & 0xffff, bs = sb >> 16;
-            const int r = s_rec[i];
+          if (rec_kind(r) == kTypeFunc) {
             const int c1 = i + 1;
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
+            int cc = own_code(r);
             if (rec_arity(r) == 1) {
-              if (!l1) s_sb[c1] = sb;
+              cc += l1 ? 1 : 0;  // LD of the leaf operand
             } else {
-              const int c2 = c1 + s_sz[c1];
-              const bool l2 = rec_kind(s_rec[c2]) != kTypeFunc;
-              if (l1 && !l2) s_sb[c2] = sb;
-              else if (!l1 && l2) s_sb[c1] = sb;
-              else if (!l1 && !l2) {
-                const int nc1 = s_nc[c1], nc2 = s_nc[c2];
-                const bool f1 = (nc1 >> 16) >= (nc2 >> 16);
-                const int F = f1 ? c1 : c2, S = f1 ? c2 : c1;
-                const int csF = (f1 ? nc1 : nc2) & 0xffff;
-                s_sb[F] = sb;
-                s_sb[S] = (st + csF + 1) | ((bs + 1) << 16);
-              }
+              const bool l2 = rec_kind(s_rec[c1 + s_sz[c1]]) != kTypeFunc;
+              cc += (l1 && l2) ? 1 : 0;    // LD of the first leaf
+              cc += (!l1 && !l2) ? 1 : 0;  // spill of the first-evaluated child
             }
-            done = true;
+            x = cc | (1 << 16);
           }
         }
-        __syncthreads();
-        if (__all(done)) break;
+        const int incl = wave_incl_scan(x, lane);
+        if (i < len) s_E[i + 1] = acc + incl;
+        acc += __shfl(incl, kWave - 1, kWave);
+      }
+      if (lane == 0) s_E[0] = 0;
+    }
+    for (int ch = 0; ch * kWave <= len; ++ch) {
+      const int i = ch * kWave + lane;
+      if (i <= len) s_D[i] = 0;
+    }
+    __syncthreads();
+
+    // ---- pass 5: ancestor terms on child ranges ----
+    // For a node whose two children are both function nodes:
+    //   forward code: the larger child F runs first (ties: first child), then
+    //   its value is spilled to slot base, then the smaller child S runs with
+    //   base + 1; every node in S's range starts (code size of F) + 1 words
+    //   later and one spill slot higher;
+    //   adjoint records: the smaller child's records come first (ties: first
+    //   child); when that is the second child, records in its range move back
+    //   by the first child's function count and records in the first child's
+    //   range move forward by the second child's.
+    int max_base = -1;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int i = ch * kWave + lane;
+      if (i >= len) continue;
+      const int r = s_rec[i];
+      if (rec_kind(r) != kTypeFunc || rec_arity(r) != 2) continue;
+      const int c1 = i + 1, z1 = s_sz[c1], c2 = c1 + z1, z2 = s_sz[c2];
+      if (rec_kind(s_rec[c1]) != kTypeFunc || rec_kind(s_rec[c2]) != kTypeFunc) continue;
+      const bool f1 = z1 >= z2;
+      const int F = f1 ? c1 : c2, zF = f1 ? z1 : z2;
+      const int S = f1 ? c2 : c1, zS = f1 ? z2 : z1;
+      const int csF = (s_E[F + zF] - s_E[F]) & 0xffff;
+      const int v = (csF + 1) + (1 << kStartBits);
+      atomicAdd(&s_D[S], v);
+      atomicAdd(&s_D[S + zS], -v);
+      if (a.adj && z2 < z1) {
+        const int n1 = (s_E[c2] - s_E[c1]) >> 16, n2 = (s_E[c2 + z2] - s_E[c2]) >> 16;
+        atomicAdd(&s_D[c2], -(n1 << 16));
+        atomicAdd(&s_D[c2 + z2], n1 << 16);
+        atomicAdd(&s_D[c1], n2 << 16);
+        atomicAdd(&s_D[c2], -(n2 << 16));
       }
     }
+    __syncthreads();
+    // inclusive scan of D: at every node, the sum of its ancestors' terms
+    {
+      int acc = 0;
+      for (int ch = 0; ch < nch; ++ch) {
+        const int i = ch * kWave + lane;
+        const int x = i < len ? s_D[i] : 0;
+        const int incl = wave_incl_scan(x, lane);
+        if (i < len) {
+          const int d = acc + incl;
+          s_D[i] = d;
+          if (rec_kind(s_rec[i]) == kTypeFunc && rec_arity(s_rec[i]) == 2) {
+            // a node that spills uses slot base
+            const int c1 = i + 1, c2 = c1 + s_sz[c1];
+            if (rec_kind(s_rec[c1]) == kTypeFunc && rec_kind(s_rec[c2]) == kTypeFunc)
+              max_base = max(max_base, (d >> kStartBits) & 15);
+          }
+        }
+        acc += __shfl(incl, kWave - 1, kWave);
+      }
+    }
+    __syncthreads();
+    const int root = s_rec[0];
+    need0 = wave_max(max_base) + 1;
+    prog_len = rec_kind(root) == kTypeFunc ? (s_E[len] & 0xffff) + 1 : 2;
+    n_int = s_E[len] >> 16;
 
     // ---- pass 6: emission ----
     if (rec_kind(root) != kTypeFunc) {
       if (lane == 0) {
         int src; float pay;
-        leaf_src(root, s_val, 0, src, pay);
+        leaf_src(root, vrow[0], src, pay);
         put(prog, a.pstride, 0, mkword(kLD + src), pay);
       }
     }
-    for (int base = 0; base < len; base += kWave) {
-      const int i = base + lane;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int i = ch * kWave + lane;
       if (i >= len) continue;
       const int r = s_rec[i];
       if (rec_kind(r) != kTypeFunc) continue;
-      const int sb = s_sb[i];
-      const int st = sb & 0xffff, bs = sb >> 16;
-      const int cs = s_nc[i] & 0xffff;
+      const int sb = s_D[i];
+      const int st = sb & ((1 << kStartBits) - 1), bs = (sb >> kStartBits) & 15;
+      const int cs = (s_E[i + s_sz[i]] - s_E[i]) & 0xffff;
       const int oc = own_code(r);
-      int pos = st + cs - oc;  // first own instruction
+      const int pos = st + cs - oc;  // first own instruction
       const int op = rec_op(r);
       const int mo = rec_modi(r);
       const int c1 = i + 1;
@@ -371,7 +398,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (rec_arity(r) == 1) {
         if (l1) {
           int src; float pay;
-          leaf_src(r1, s_val, c1, src, pay);
+          leaf_src(r1, vrow[c1], src, pay);
           put(prog, a.pstride, st, mkword(kLD + src), pay);
         }
         if (mo < 0) {
@@ -382,7 +409,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         }
         continue;
       }
-      const int c2 = c1 + s_sz[c1];
+      const int z1 = s_sz[c1];
+      const int c2 = c1 + z1;
       const int r2 = s_rec[c2];
       const bool l2 = rec_kind(r2) != kTypeFunc;
       int src, aux = 0;
@@ -390,26 +418,26 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       bool a_first;  // A holds the first operand and src the second
       if (l1 && l2) {
         int s1; float p1;
-        leaf_src(r1, s_val, c1, s1, p1);
+        leaf_src(r1, vrow[c1], s1, p1);
         put(prog, a.pstride, st, mkword(kLD + s1), p1);
-        leaf_src(r2, s_val, c2, src, pay);
+        leaf_src(r2, vrow[c2], src, pay);
         a_first = true;
       } else if (l1) {
-        leaf_src(r1, s_val, c1, src, pay);
+        leaf_src(r1, vrow[c1], src, pay);
         a_first = false;
       } else if (l2) {
-        leaf_src(r2, s_val, c2, src, pay);
+        leaf_src(r2, vrow[c2], src, pay);
         a_first = true;
       } else {
-        const int nc1 = s_nc[c1], nc2 = s_nc[c2];
-        const bool f1 = (nc1 >> 16) >= (nc2 >> 16);
-        const int csF = (f1 ? nc1 : nc2) & 0xffff;
+        const bool f1 = z1 >= s_sz[c2];
+        const int F = f1 ? c1 : c2;
+        const int csF = (s_E[F + s_sz[F]] - s_E[F]) & 0xffff;
         int saux;
         if (bs < kRegSlots) put(prog, a.pstride, st + csF, mkword(kSPL + bs), 0.0f);
         else put(prog, a.pstride, st + csF, mkword(kSPLM, bs), 0.0f);
         src = src_slot(bs, saux);
         aux = saux;
-        a_first = !f1;  // first-evaluated child is in the slot
+        a_first = !f1;  // the first-evaluated child is in the slot
       }
       if (mo >= 0) {
         put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
@@ -428,80 +456,34 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     }
 
     // ---- pass 7: adjoint records (gradient calls only) ----
+    // Record q of a function node: its position in a pre-order walk that
+    // visits the smaller child first = (function nodes before it in the
+    // array) + (its ancestors' shifts). A record whose node is the
+    // later-visited child of a node with two function children takes its
+    // adjoint from the pending stack ("pop"); that parent pushes it.
     if (a.adj) {
-      // bottom-up: number of function nodes in each subtree
-      for (int base = 0; base < len; base += kWave) {
-        const int i = base + lane;
-        if (i < len) s_ai[i] = rec_kind(s_rec[i]) == kTypeFunc ? -1 : 0;
-      }
-      __syncthreads();
-      for (int ch = nch - 1; ch >= 0; --ch) {
+      uint32_t* recs = a.adj + t * (int64_t)Lmax * kAdjWords;
+      for (int ch = 0; ch < nch; ++ch) {
         const int i = ch * kWave + lane;
-        bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
-        for (int it = 0; it <= kWave; ++it) {
-          if (!done) {
-            const int c1 = i + 1;
-            const int a1 = s_ai[c1];
-            int a2 = 0;
-            if (rec_arity(s_rec[i]) == 2) a2 = s_ai[c1 + s_sz[c1]];
-            if (a1 >= 0 && a2 >= 0) {
-              s_ai[i] = 1 + a1 + a2;
-              done = true;
-            }
-          }
-          __syncthreads();
-          if (__all(done)) break;
-        }
+        if (i >= len) continue;
+        const int r = s_rec[i];
+        if (rec_kind(r) != kTypeFunc || rec_arity(r) != 2) continue;
+        const int c1 = i + 1, z1 = s_sz[c1], c2 = c1 + z1;
+        if (rec_kind(s_rec[c1]) != kTypeFunc || rec_kind(s_rec[c2]) != kTypeFunc) continue;
+        atomicOr(&s_rec[s_sz[c2] < z1 ? c1 : c2], kRecPop);
       }
-      n_int = rec_kind(root) == kTypeFunc ? s_ai[0] : 0;
-      __syncthreads();
-      // top-down: record position and pending flag (smaller child first)
-      if (lane == 0 && rec_kind(root) == kTypeFunc) s_ai[0] = 0 | (1 << 30);
       __syncthreads();
       for (int ch = 0; ch < nch; ++ch) {
         const int i = ch * kWave + lane;
-        bool done = !(i < len && rec_kind(s_rec[i]) == kTypeFunc);
-        for (int it = 0; it <= kWave; ++it) {
-          if (!done) {
-            const int qi = s_ai[i];
-            if (qi & (1 << 30)) {
-              const int q = qi & 0xffff;
-              const int c1 = i + 1;
-              const bool f1 = rec_kind(s_rec[c1]) == kTypeFunc;
-              if (rec_arity(s_rec[i]) == 1) {
-                if (f1) s_ai[c1] = (q + 1) | (1 << 30);
-              } else {
-                const int c2 = c1 + s_sz[c1];
-                const bool f2 = rec_kind(s_rec[c2]) == kTypeFunc;
-                const bool c2first = s_sz[c2] < s_sz[c1];
-                const int F = c2first ? c2 : c1, S = c2first ? c1 : c2;
-                const bool fF = c2first ? f2 : f1, fS = c2first ? f1 : f2;
-                const int nF = fF ? s_ai[F] : 0;
-                if (fF) s_ai[F] = (q + 1) | (1 << 30);
-                if (fS) s_ai[S] = (q + 1 + nF) | (1 << 30) | (fF ? (1 << 16) : 0);
-              }
-              done = true;
-            }
-          }
-          __syncthreads();
-          if (__all(done)) break;
-        }
-      }
-      // emission
-      uint32_t* recs = a.adj + t * (int64_t)Lmax * kAdjWords;
-      for (int base = 0; base < len; base += kWave) {
-        const int i = base + lane;
         if (i >= len) continue;
         const int r = s_rec[i];
         if (rec_kind(r) != kTypeFunc) continue;
-        const int qi = s_ai[i];
-        const int q = qi & 0xffff;
-        if (q >= Lmax) continue;
-        const int pop = (qi >> 16) & 1;
+        const int q = (s_D[i] >> 16) + (s_E[i] >> 16);
+        if (q < 0 || q >= Lmax) continue;
         const int ar = rec_arity(r);
         const int c1 = i + 1;
         const int c2 = ar == 2 ? c1 + s_sz[c1] : -1;
-        uint32_t wv[kAdjWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t wv[5] = {0, 0, 0, 0, 0};
         int kinds[2] = {kKindNone, kKindNone}, vars[2] = {0, 0};
         const int ch2[2] = {c1, c2};
         bool both_func = ar == 2;
@@ -510,8 +492,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           const int rc = s_rec[c];
           if (rec_kind(rc) == kTypeFunc) {
             kinds[k] = kKindFunc;
-            wv[1 + 2 * k] = (uint32_t)(s_sb[c] & 0xffff);
-            wv[2 + 2 * k] = (uint32_t)(s_nc[c] & 0xffff);
+            wv[1 + 2 * k] = (uint32_t)(s_D[c] & ((1 << kStartBits) - 1));
+            wv[2 + 2 * k] = (uint32_t)((s_E[c + s_sz[c]] - s_E[c]) & 0xffff);
           } else if (rec_kind(rc) == kTypeVar) {
             kinds[k] = kKindVar;
             vars[k] = rec_var(rc);
@@ -519,11 +501,12 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           } else {
             kinds[k] = kKindConst;
             wv[1 + 2 * k] = (uint32_t)c;
-            wv[2 + 2 * k] = __float_as_uint(s_val[c]);
+            wv[2 + 2 * k] = __float_as_uint(vrow[c]);
             both_func = false;
           }
         }
         const int c2first = (ar == 2 && s_sz[c2] < s_sz[c1]) ? 1 : 0;
+        const int pop = (r & kRecPop) ? 1 : 0;
         wv[0] = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) | (c2first << 7) |
                            (pop << 8) | ((both_func ? 1 : 0) << 9) | (kinds[0] << 10) | (kinds[1] << 12) |
                            (vars[0] << 14) | (vars[1] << 18));
@@ -549,7 +532,6 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     info[kInfoNeed] = need0;
     info[kInfoNInternal] = n_int;
     a.acc[t] = 0.0;
-    if (a.hist && status == 0) atomicAdd(&a.hist[bucket], 1);
     if (a.out_status) a.out_status[t] = status;
     if (a.out_info) {
       int32_t* o = a.out_info + t * 6;
@@ -563,24 +545,53 @@ __global__ void prep_kernel(int32_t* c, int n) {
   if (i < n) c[i] = 0;
 }
 
-// Counting sort of the trees by length bucket, longest bucket first, invalid trees last.
-__global__ void order_kernel(OrderArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.P) return;
-  const int32_t* inf = a.info + t * kInfoStride;
-  int pos;
-  if (inf[kInfoStatus] != 0) {
-    // invalid trees go after every valid one (the evaluators skip them)
-    int nvalid = 0;
-    for (int k = 0; k < 16; ++k) nvalid += a.hist[k];
-    pos = nvalid + atomicAdd(&a.cursor[16], 1);
-  } else {
-    const int b = inf[kInfoBucket];
-    int off = 0;
-    for (int k = 15; k > b; --k) off += a.hist[k];
-    pos = off + atomicAdd(&a.cursor[b], 1);
+// Counting sort of the trees by length bucket, longest bucket first,
+// invalid trees last. Two kernels of 256 trees per workgroup; each
+// workgroup aggregates its counts in LDS and issues one global atomic per
+// bucket it holds (one cache line of counters would otherwise take one
+// atomic per tree).
+constexpr int kOrderBlock = 256;
+constexpr int kKeys = 17;  // 16 length buckets + invalid trees
+
+__device__ __forceinline__ int order_key(const int32_t* info, int64_t t) {
+  const int32_t* inf = info + t * kInfoStride;
+  return inf[kInfoStatus] != 0 ? 16 : inf[kInfoBucket];
+}
+
+__global__ __launch_bounds__(kOrderBlock) void hist_kernel(OrderArgs a) {
+  __shared__ int cnt[kKeys];
+  if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+  if (t < a.P) {
+    const int k = order_key(a.info, t);
+    if (k < 16) atomicAdd(&cnt[k], 1);
   }
-  a.order[pos] = (int32_t)t;
+  __syncthreads();
+  if (threadIdx.x < 16 && cnt[threadIdx.x] > 0) atomicAdd(&a.hist[threadIdx.x], cnt[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(kOrderBlock) void order_kernel(OrderArgs a) {
+  __shared__ int cnt[kKeys], base[kKeys];
+  if (threadIdx.x < kKeys) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kOrderBlock + threadIdx.x;
+  int k = -1, rank = 0;
+  if (t < a.P) {
+    k = order_key(a.info, t);
+    rank = atomicAdd(&cnt[k], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < kKeys) {
+    const int key = threadIdx.x;
+    // first slot of this key: buckets longer than it, or every valid tree for invalid ones
+    int off = 0;
+    for (int b = 15; b >= 0; --b)
+      if (b > key || key == 16) off += a.hist[b];
+    base[key] = cnt[key] > 0 ? off + atomicAdd(&a.cursor[key], cnt[key]) : 0;
+  }
+  __syncthreads();
+  if (k >= 0) a.order[base[k] + rank] = (int32_t)t;
 }
 
 hipError_t launch_prep(int32_t* counters, int n, hipStream_t s) {
@@ -590,13 +601,21 @@ hipError_t launch_prep(int32_t* counters, int n, hipStream_t s) {
 
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {
   if (a.P <= 0) return hipSuccess;
-  plan_kernel<<<dim3((unsigned)a.P), dim3(64), plan_lds_bytes(a.Lmax), s>>>(a);
+  const dim3 grid((unsigned)a.P), block(64);
+  const size_t lds = plan_lds_bytes(a.Lmax);
+  if (a.Lmax <= 64) plan_kernel<1><<<grid, block, lds, s>>>(a);
+  else if (a.Lmax <= 128) plan_kernel<2><<<grid, block, lds, s>>>(a);
+  else if (a.Lmax <= 256) plan_kernel<4><<<grid, block, lds, s>>>(a);
+  else if (a.Lmax <= 512) plan_kernel<8><<<grid, block, lds, s>>>(a);
+  else plan_kernel<kMaxLmax / kWave><<<grid, block, lds, s>>>(a);
   return hipGetLastError();
 }
 
 hipError_t launch_order(const OrderArgs& a, hipStream_t s) {
   if (a.P <= 0) return hipSuccess;
-  order_kernel<<<(unsigned)((a.P + 255) / 256), 256, 0, s>>>(a);
+  const unsigned grid = (unsigned)((a.P + kOrderBlock - 1) / kOrderBlock);
+  hist_kernel<<<grid, kOrderBlock, 0, s>>>(a);
+  order_kernel<<<grid, kOrderBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -23,15 +23,19 @@ struct PlanArgs {
   int64_t pstride;
   double* acc;          // [P], zeroed by the plan
   uint32_t* adj;        // optional [P][Lmax][kAdjWords] adjoint records
-  int32_t* hist;        // [16] length-bucket histogram (may be null)
   int32_t* out_info;    // optional [P][6]
   int32_t* out_status;  // optional [P]
 };
 
+// persistent work queues: one counter per XCD-sized share of the grid, each
+// in its own cache line, so that the unit counters are not one hot line
+constexpr int kMaxQueues = 8;
+constexpr int kQueueStride = 32;
+
 struct OrderArgs {
   const int32_t* info;
   int64_t P;
-  const int32_t* hist;  // [16]
+  int32_t* hist;        // [16] valid trees per length bucket, zero on entry
   int32_t* cursor;      // [17], zero on entry (16 buckets + invalid trees)
   int32_t* order;       // [P] tree indices, longest length bucket first
 };
@@ -57,7 +61,8 @@ struct EvalArgs {
   int32_t ngroups;      // tile groups of block_waves tiles (tree-major / point-major)
   int32_t tpu;          // trees per unit
   int64_t n_units;      // persistent: number of (tree chunk, tile) units
-  int32_t* queue;       // persistent: unit counter, zero on entry
+  int32_t* queue;       // persistent: nq unit counters kQueueStride ints apart, zero on entry
+  int32_t nq;           // persistent: number of queues (workgroup b draws from queue b % nq)
 };
 
 struct AdjArgs {
