@@ -99,7 +99,7 @@ enum { TGP_FLAG_NO_TAIL_CHECK = 1 };   /* skip reading the NaN padding after len
 typedef struct tgp_cfg {
   int32_t mode;             /* TGP_MODE_*                                           */
   int32_t block_waves;      /* waves per workgroup: 1, 2 or 4                       */
-  int32_t points_per_lane;  /* data points per lane: 4 or 8                         */
+  int32_t points_per_lane;  /* data points per lane: 4, 8 (V <= 8) or 16 (V <= 2)  */
   int32_t trees_per_unit;   /* trees handled per work unit (point-major, persistent) */
   int32_t flags;            /* TGP_FLAG_*                                           */
 } tgp_cfg;

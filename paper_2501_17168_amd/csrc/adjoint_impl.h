@@ -73,10 +73,6 @@ __device__ __forceinline__ void partials(int op, float a, float b, float& da, fl
   }
 }
 
-__device__ __forceinline__ float wave_sum_f32(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
 
 template <int K, int VM>
 struct AdjState {

@@ -99,7 +99,10 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
       c.flags |= flags;
     }
   }
-  if ((c.points_per_lane != 4 && c.points_per_lane != 8) || d->V > 8) c.points_per_lane = d->V > 8 ? 4 : 8;
+  // K = 16 exists for up to 2 variables, K = 8 for up to 8, K = 4 for all
+  const int kmax = d->V <= 2 ? 16 : (d->V <= 8 ? 8 : 4);
+  if (c.points_per_lane != 4 && c.points_per_lane != 8 && c.points_per_lane != 16) c.points_per_lane = std::min(8, kmax);
+  c.points_per_lane = std::min(c.points_per_lane, kmax);
   const int64_t tile = 64LL * c.points_per_lane;
   const int64_t ntiles = (d->D + tile - 1) / tile;
   if (c.mode < TGP_MODE_TREE_MAJOR || c.mode > TGP_MODE_PERSISTENT)

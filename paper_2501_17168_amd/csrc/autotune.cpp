@@ -53,8 +53,9 @@ tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, tgp_cf
     return TGP_E_HIP;
   }
   std::vector<tgp_cfg> cands;
-  const int ks[2] = {8, 4};
+  const int ks[3] = {16, 8, 4};
   for (int k : ks) {
+    if (k == 16 && d->V > 2) continue;
     if (k == 8 && d->V > 8) continue;
     for (int bw : {1, 2, 4}) cands.push_back(tgp_cfg{TGP_MODE_TREE_MAJOR, bw, k, 1, 0});
     for (int tpu : {1, 4, 16, 64})

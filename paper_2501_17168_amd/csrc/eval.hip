@@ -21,6 +21,7 @@ __global__ void finalize_kernel(FinalArgs a) {
 hipError_t launch_eval(const EvalArgs& a, int K, int VM, int NO, bool pred, int block_waves, int64_t grid,
                        hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  if (K == 16 && VM == 2) return launch_eval_kv<16, 2>(a, NO, pred, block_waves, grid, s);
   if (K == 8) {
     switch (VM) {
       case 2: return launch_eval_kv<8, 2>(a, NO, pred, block_waves, grid, s);

@@ -32,6 +32,28 @@ namespace {
 
 using namespace interp;
 
+// Sum of this lane's K squared residuals: pairwise in float32 (relative
+// error below 3 ulp for K <= 8, all terms non-negative), widened to float64
+// for the wave and cross-wave sums; summed in float64 instead if the
+// float32 sum overflows while the terms do not.
+template <int K>
+__device__ __forceinline__ double lane_sum_sq(float (&sq)[K]) {
+  float t[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) t[j] = sq[j];
+#pragma unroll
+  for (int w = K / 2; w >= 1; w /= 2)
+#pragma unroll
+    for (int j = 0; j < w; ++j) t[j] += t[j + w];
+  double r = (double)t[0];
+  if (__builtin_expect(isinf(t[0]), 0)) {
+    r = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) r += (double)sq[j];
+  }
+  return r;
+}
+
 template <int K, int VM, int NO>
 __device__ __forceinline__ void load_x(const EvalArgs& a, Regs<K, VM, NO>& s, int64_t p0) {
 #pragma unroll
@@ -97,14 +119,14 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
       }
       if (a.Y) {
         const float* yr = a.Y + (int64_t)o * a.ldy;
+        float sq[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int64_t p = p0 + j * kWave;
-          if (p < a.D) {
-            const float e = s.O[o][j] - yr[p];
-            sse += (double)(e * e);
-          }
+          const float e = p < a.D ? s.O[o][j] - yr[p] : 0.0f;
+          sq[j] = e * e;
         }
+        sse += lane_sum_sq<K>(sq);
       }
     }
   }

@@ -1,0 +1,6 @@
+// Instantiation of the forward-evaluation kernels for K = 16 points per lane, up to 2 input variables.
+#include "eval_impl.h"
+
+namespace tgp {
+template hipError_t launch_eval_kv<16, 2>(const EvalArgs&, int, bool, int, int64_t, hipStream_t);
+}  // namespace tgp

@@ -15,6 +15,9 @@ constexpr int kWave = 64;
 template <int K>
 constexpr int kLdsFloatsPerWave = (kMaxSlots - kRegSlots) * K * kWave;
 
+// interpreter actions after the dispatch switch
+constexpr int kActModi = 8, kActUn = 16, kActStop = 32;
+
 template <int K, int VM, int NO>
 struct Regs {
   float A[K];
@@ -86,9 +89,11 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
   if (BOUNDED && count <= 0) return;
   unsigned long long ins = prog[0];
   asm volatile("" : "+s"(ins));
+  int left = count;
   // one exit (after the latch), so the loop is a single-entry single-exit
-  // region made only of uniform branches
-  bool done = false;
+  // region made only of uniform branches. `act` (scalar) is 0 for the
+  // common case; otherwise it carries a unary function to apply
+  // (kActUn | index, kActModi for the Modi register) and/or kActStop.
   for (;;) {
     ++prog;
     const unsigned long long nxt = prog[0];
@@ -96,7 +101,7 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
     const float cv = __uint_as_float((uint32_t)(ins >> 32));
     const int c = (int)(w & 0xffffu);
     const int aux = (int)(w >> 16);
-    int un = -1;
+    int act = 0;
 
 #define TGP_SRC_CASE(BASE, S, STMT)                                   \
   case (BASE) + (S): {                                                \
@@ -138,12 +143,12 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
 // library implementations branch per lane, and keeping those divergent
 // branches out of the dispatch switch keeps the switch a purely scalar
 // branch tree (no per-lane flow merges that copy the register state).
-#define TGP_UN_CASE(U)     \
-  case kUN + (U):          \
-    un = (U);              \
-    break;                 \
-  case kMU + (U):          \
-    un = (U) | 8;          \
+#define TGP_UN_CASE(U)          \
+  case kUN + (U):               \
+    act = kActUn | (U);         \
+    break;                      \
+  case kMU + (U):               \
+    act = kActUn | kActModi | (U); \
     break;
 
     switch (c) {
@@ -196,60 +201,105 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
         add_out<K, VM, NO>(s, aux);
         break;
       default:  // kEND (or any word that is not an instruction)
-        done = true;
+        act = kActStop;
         break;
     }
 #undef TGP_SRC_CASE
 #undef TGP_SRC_CASES
 #undef TGP_BT_CASE
 #undef TGP_UN_CASE
-    if (un >= 0) {
-      float t[K];
-      switch (un & 7) {
-        case 0:
+    if (BOUNDED) {
+      if (--left == 0) act |= kActStop;
+    }
+    // keep act an opaque scalar: otherwise the compiler threads the per-case
+    // constants through boolean phis held as 64-bit lane masks
+    asm volatile("" : "+s"(act));
+    if (act) {
+      if (act & kActUn) {
+        float t[K];
+        switch (act & 7) {
+          case 0:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<0>(s.A[j]);
-          break;
-        case 1:
+            for (int j = 0; j < K; ++j) t[j] = un_op<0>(s.A[j]);
+            break;
+          case 1:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<1>(s.A[j]);
-          break;
-        case 2:
+            for (int j = 0; j < K; ++j) t[j] = un_op<1>(s.A[j]);
+            break;
+          case 2:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<2>(s.A[j]);
-          break;
-        case 3:
+            for (int j = 0; j < K; ++j) t[j] = un_op<2>(s.A[j]);
+            break;
+          case 3:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<3>(s.A[j]);
-          break;
-        case 4:
+            for (int j = 0; j < K; ++j) t[j] = un_op<3>(s.A[j]);
+            break;
+          case 4:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<4>(s.A[j]);
-          break;
-        default:
+            for (int j = 0; j < K; ++j) t[j] = un_op<4>(s.A[j]);
+            break;
+          default:
 #pragma unroll
-          for (int j = 0; j < K; ++j) t[j] = un_op<5>(s.A[j]);
-          break;
-      }
-      if (un & 8) {
+            for (int j = 0; j < K; ++j) t[j] = un_op<5>(s.A[j]);
+            break;
+        }
+        if (act & kActModi) {
 #pragma unroll
-        for (int j = 0; j < K; ++j) s.r[j] = t[j];
-      } else {
+          for (int j = 0; j < K; ++j) s.r[j] = t[j];
+        } else {
 #pragma unroll
-        for (int j = 0; j < K; ++j) s.A[j] = t[j];
+          for (int j = 0; j < K; ++j) s.A[j] = t[j];
+        }
       }
     }
-    if (BOUNDED) done = done || (--count == 0);
     unsigned long long n2 = nxt;
     asm volatile("" : "+s"(n2));
     ins = n2;
-    if (done) break;
+    if (act & kActStop) break;
   }
 }
 
+// 64-bit DPP move: row_shr / row_bcast as in the GCN data-parallel
+// primitives; lanes with no source, or outside row_mask, read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Sum over the 64 lanes (all active), returned in every lane: row shifts by
+// 1, 2, 4, 8 leave each row's sum in its lane 15; two row broadcasts carry
+// the row sums up to lane 63. VALU only (no LDS round trips).
+constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_f64<kRowShr + 1, 0xf>(v);
+  v += dpp_f64<kRowShr + 2, 0xf>(v);
+  v += dpp_f64<kRowShr + 4, 0xf>(v);
+  v += dpp_f64<kRowShr + 8, 0xf>(v);
+  v += dpp_f64<kRowBcast15, 0xa>(v);
+  v += dpp_f64<kRowBcast31, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  v += dpp_f32<kRowShr + 1, 0xf>(v);
+  v += dpp_f32<kRowShr + 2, 0xf>(v);
+  v += dpp_f32<kRowShr + 4, 0xf>(v);
+  v += dpp_f32<kRowShr + 8, 0xf>(v);
+  v += dpp_f32<kRowBcast15, 0xa>(v);
+  v += dpp_f32<kRowBcast31, 0xc>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 }  // namespace interp

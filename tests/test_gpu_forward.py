@@ -124,7 +124,7 @@ MODES = [("tree", dict(mode=1)), ("tree-bw1", dict(mode=1, block_waves=1)), ("po
          ("persist-tpu1", dict(mode=3, trees_per_unit=1))]
 
 
-@pytest.mark.parametrize("K", [8, 4])
+@pytest.mark.parametrize("K", [16, 8, 4])
 @pytest.mark.parametrize("mode", [m[0] for m in MODES])
 @pytest.mark.parametrize("name", list(SMALL))
 def test_forward_parity(name, mode, K):
@@ -209,7 +209,7 @@ def _complete_tree(depth, rng, Lmax):
     return t, v, s
 
 
-@pytest.mark.parametrize("K", [8, 4])
+@pytest.mark.parametrize("K", [16, 8, 4])
 def test_edge_shapes(K):
     r = np.random.default_rng(5)
     Lmax = 1024
