@@ -164,19 +164,22 @@ tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
 const char* tgp_status_str(tgp_status s);
 
 /* ---- measurement helpers (not part of the evaluated method) ----
- * tgp_op_rate: throughput, in applications per second, of op id `op`
- *   (0..11) in a straight-line compiled loop (8 independent chains per
- *   lane, full occupancy) on the current device; the rate relative to add
- *   is the operator's cost in vector-ALU issue slots. Synchronous; it
- *   allocates and frees a small device buffer. Returns TGP_E_ARG for a bad
- *   op or null output.
+ * tgp_op_cost: cost of op id `op` (0..11) in vector-ALU issue slots per
+ *   application and lane, measured on the current device: a straight-line
+ *   compiled loop applies the operator to 8 independent streams of spread
+ *   inputs per lane (fresh values each step, x in [-8, 8), [-20, 20) for
+ *   exp, so lanes take data-dependent branches as on real data); its time
+ *   above the same loop without the operator, divided by the time of one
+ *   issue slot (from the same loop with 32 dependent FMAs added), is the
+ *   cost. Synchronous; it allocates and frees a small
+ *   device buffer. Returns TGP_E_ARG for a bad op or null output.
  * tgp_profile(enable): while enabled, every forward call records a HIP
  *   event pair around its evaluation-kernel launch on the caller's stream
  *   (creating the two events on the host).
  * tgp_profile_read: waits for the recorded events, returns the summed
  *   evaluation-kernel time in ms and the number of launches, and clears
  *   the record. */
-tgp_status tgp_op_rate(int32_t op, double* ops_per_s);
+tgp_status tgp_op_cost(int32_t op, double* slots);
 tgp_status tgp_profile(int32_t enable);
 tgp_status tgp_profile_read(double* total_ms, int64_t* launches);
 

@@ -23,7 +23,7 @@ FLAG_NO_TAIL_CHECK = 1
 
 # symbols the header declares; the CPU tests check that each one is exported
 EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output",
-           "tgp_eval_mse_grad", "tgp_autotune", "tgp_status_str", "tgp_op_rate", "tgp_profile",
+           "tgp_eval_mse_grad", "tgp_autotune", "tgp_status_str", "tgp_op_cost", "tgp_profile",
            "tgp_profile_read")
 
 
@@ -82,8 +82,8 @@ def load():
     lib.tgp_eval_mse_grad.restype = i32
     lib.tgp_autotune.argtypes = [P(TgpPop), P(TgpData), i32, i32, P(TgpCfg), vp, ctypes.c_size_t, vp]
     lib.tgp_autotune.restype = i32
-    lib.tgp_op_rate.argtypes = [i32, P(ctypes.c_double)]
-    lib.tgp_op_rate.restype = i32
+    lib.tgp_op_cost.argtypes = [i32, P(ctypes.c_double)]
+    lib.tgp_op_cost.restype = i32
     lib.tgp_profile.argtypes = [i32]
     lib.tgp_profile.restype = i32
     lib.tgp_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64)]
@@ -106,10 +106,10 @@ def check(code, where):
         raise TgpError(code, where)
 
 
-def op_rate(op):
-    """Applications per second of op id `op` in a compiled straight-line loop (device measurement)."""
+def op_cost(op):
+    """Cost of operator `op` in vector-ALU issue slots, measured on the current device."""
     r = ctypes.c_double()
-    check(load().tgp_op_rate(int(op), ctypes.byref(r)), "tgp_op_rate")
+    check(load().tgp_op_cost(int(op), ctypes.byref(r)), "tgp_op_cost")
     return r.value
 
 

@@ -32,12 +32,10 @@ namespace {
 
 using namespace interp;
 
-// Sum of this lane's K squared residuals: pairwise in float32 (relative
-// error below 3 ulp for K <= 8, all terms non-negative), widened to float64
-// for the wave and cross-wave sums; summed in float64 instead if the
-// float32 sum overflows while the terms do not.
+// Sum of this lane's K squared residuals, pairwise in float32 (all terms
+// are non-negative, so the relative error is below log2(K) ulp).
 template <int K>
-__device__ __forceinline__ double lane_sum_sq(float (&sq)[K]) {
+__device__ __forceinline__ float lane_sum_sq(const float (&sq)[K]) {
   float t[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) t[j] = sq[j];
@@ -45,13 +43,7 @@ __device__ __forceinline__ double lane_sum_sq(float (&sq)[K]) {
   for (int w = K / 2; w >= 1; w /= 2)
 #pragma unroll
     for (int j = 0; j < w; ++j) t[j] += t[j + w];
-  double r = (double)t[0];
-  if (__builtin_expect(isinf(t[0]), 0)) {
-    r = 0.0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) r += (double)sq[j];
-  }
-  return r;
+  return t[0];
 }
 
 template <int K, int VM, int NO>
@@ -72,7 +64,20 @@ __device__ __forceinline__ void load_x(const EvalArgs& a, Regs<K, VM, NO>& s, in
   }
 }
 
+// Output o of the tree at point slot j: a tree without Modi nodes predicts
+// (root, 0, ..., 0); the root value is the accumulator A.
+template <int K, int VM, int NO>
+__device__ __forceinline__ float out_val(const Regs<K, VM, NO>& s, int nmodi, int o, int j) {
+  return nmodi ? s.O[o][j] : (o == 0 ? s.A[j] : 0.0f);
+}
+
 // Evaluate tree t on the tile whose first point for this lane is p0.
+//
+// Fitness reduction: squared residuals in float32, summed pairwise per lane
+// and over the wave by DPP (all terms non-negative: relative error below
+// (log2 K + 6) float32 ulp, under 6e-7), then added in float64 across
+// waves. If the float32 wave sum overflows, the tile is summed again in
+// float64 (terms that are themselves infinite give the same result).
 template <int K, int VM, int NO, bool PRED>
 __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, float* spill, int64_t t,
                                           int64_t p0, int lane) {
@@ -92,48 +97,63 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
     return;
   }
   const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
+  if (nmodi) {
 #pragma unroll
-  for (int q = 0; q < NO; ++q)
+    for (int q = 0; q < NO; ++q)
 #pragma unroll
-    for (int j = 0; j < K; ++j) s.O[q][j] = 0.0f;
-#pragma unroll
-  for (int j = 0; j < K; ++j) s.A[j] = 0.0f;
-  run_program<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), s, spill);
-  // outputs: a tree without Modi nodes predicts (root, 0, ..., 0)
-  if (nmodi == 0) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) s.O[0][j] = s.A[j];
+      for (int j = 0; j < K; ++j) s.O[q][j] = 0.0f;
   }
+  // every program starts by loading A
+  run_program<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), s, spill);
 
-  double sse = 0.0;
+  if constexpr (PRED) {
 #pragma unroll
-  for (int o = 0; o < NO; ++o) {
-    if (o < a.n_out) {
-      if constexpr (PRED) {
+    for (int o = 0; o < NO; ++o) {
+      if (o < a.n_out) {
         float* pr = a.pred + (t * a.n_out + o) * a.ldp;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int64_t p = p0 + j * kWave;
-          if (p < a.D) pr[p] = s.O[o][j];
+          if (p < a.D) pr[p] = out_val(s, nmodi, o, j);
         }
-      }
-      if (a.Y) {
-        const float* yr = a.Y + (int64_t)o * a.ldy;
-        float sq[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int64_t p = p0 + j * kWave;
-          const float e = p < a.D ? s.O[o][j] - yr[p] : 0.0f;
-          sq[j] = e * e;
-        }
-        sse += lane_sum_sq<K>(sq);
       }
     }
   }
-  if (a.Y) {
-    sse = wave_sum_f64(sse);
-    if (lane == 0) unsafeAtomicAdd(&a.acc[t], sse);
+  if (!a.Y) return;
+  float lane_sum = 0.0f;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    if (o < a.n_out) {
+      const float* yr = a.Y + (int64_t)o * a.ldy;
+      float sq[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int64_t p = p0 + j * kWave;
+        const float e = p < a.D ? out_val(s, nmodi, o, j) - yr[p] : 0.0f;
+        sq[j] = e * e;
+      }
+      lane_sum += lane_sum_sq<K>(sq);
+    }
   }
+  const float tot32 = wave_sum_f32(lane_sum);
+  double tot = (double)tot32;
+  if (__builtin_isinf(tot32)) {
+    double l64 = 0.0;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      if (o < a.n_out) {
+        const float* yr = a.Y + (int64_t)o * a.ldy;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int64_t p = p0 + j * kWave;
+          const float e = p < a.D ? out_val(s, nmodi, o, j) - yr[p] : 0.0f;
+          l64 += (double)(e * e);
+        }
+      }
+    }
+    tot = wave_sum_f64(l64);
+  }
+  if (lane == 0) unsafeAtomicAdd(&a.acc[t], tot);
 }
 
 }  // namespace

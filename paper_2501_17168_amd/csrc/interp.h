@@ -160,6 +160,8 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
       TGP_SRC_CASES(kMIN, s.A[j] = fminf(s.A[j], v))
       TGP_SRC_CASES(kSUBA, s.A[j] = s.A[j] - v)
       TGP_SRC_CASES(kSUBR, s.A[j] = v - s.A[j])
+      TGP_SRC_CASES(kDIVA, s.A[j] = bin_op<3>(s.A[j], v))
+      TGP_SRC_CASES(kDIVR, s.A[j] = bin_op<3>(v, s.A[j]))
       case kSPL + 0:
 #pragma unroll
         for (int j = 0; j < K; ++j) s.R[0][j] = s.A[j];
@@ -216,39 +218,45 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
     asm volatile("" : "+s"(act));
     if (act) {
       if (act & kActUn) {
-        float t[K];
+        // f(A) in place; a Modi node's value goes to r while A keeps the
+        // child value it hands up
+        float keep[K];
+        if (act & kActModi) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) keep[j] = s.A[j];
+        }
         switch (act & 7) {
           case 0:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<0>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<0>(s.A[j]);
             break;
           case 1:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<1>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<1>(s.A[j]);
             break;
           case 2:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<2>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<2>(s.A[j]);
             break;
           case 3:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<3>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<3>(s.A[j]);
             break;
           case 4:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<4>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<4>(s.A[j]);
             break;
           default:
 #pragma unroll
-            for (int j = 0; j < K; ++j) t[j] = un_op<5>(s.A[j]);
+            for (int j = 0; j < K; ++j) s.A[j] = un_op<5>(s.A[j]);
             break;
         }
         if (act & kActModi) {
 #pragma unroll
-          for (int j = 0; j < K; ++j) s.r[j] = t[j];
-        } else {
-#pragma unroll
-          for (int j = 0; j < K; ++j) s.A[j] = t[j];
+          for (int j = 0; j < K; ++j) {
+            s.r[j] = s.A[j];
+            s.A[j] = keep[j];
+          }
         }
       }
     }

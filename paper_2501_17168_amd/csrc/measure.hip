@@ -1,10 +1,11 @@
 // Measurement helpers (not part of the evaluated method).
 //
-// 1. Operator throughput: a straight-line compiled loop applies one operator
-//    to 8 independent chains per lane over a full-occupancy grid, so its rate
-//    is what a compiled (not interpreted) evaluator would reach for that
-//    operator. Rates relative to add give each operator's cost in VALU
-//    issue slots, the unit of the interpreter's roofline.
+// 1. Operator cost: a straight-line compiled loop applies one operator to 8
+//    independent streams of spread inputs per lane over a full-occupancy
+//    grid. Its time above a reference loop without the operator, in units
+//    of one extra add, is the operator's cost in VALU issue slots as a
+//    compiled (not interpreted) evaluator would pay it: the unit of the
+//    interpreter's roofline.
 // 2. Kernel timing: when enabled, the forward path records a HIP event pair
 //    around each evaluation-kernel launch on the caller's stream.
 #include <hip/hip_runtime.h>
@@ -20,37 +21,61 @@ namespace tgp {
 
 namespace {
 
+// Each lane walks its own Weyl sequence u += golden-ratio constant, mapped
+// to x in [-R, R): fresh, spread inputs every step, so the lanes of a wave
+// take an operator's data-dependent branches as they would on real data
+// (iterating x = f(x) instead would converge and keep every lane on one
+// branch). OP < 0 are the references: kNull adds x; kUnit first runs x
+// through kUnitOps dependent FMAs (no folding possible), so (kUnit - kNull)
+// / kUnitOps is the time of one issue slot. (A single extra instruction
+// partly hides in the loop's latency and would understate the slot.)
+constexpr int kNull = -2, kUnit = -1, kUnitOps = 32;
+
 template <int OP>
-__device__ __forceinline__ float step(float x, float y) {
-  if constexpr (OP == kOpAdd) return x + y;
-  else if constexpr (OP == kOpSub) return x - y;
-  else if constexpr (OP == kOpMul) return x * y;
-  else if constexpr (OP == kOpDiv) return fabsf(x) < kDivTau ? 1.0f : y / x;          // x <- 1.3 / x
+__device__ __forceinline__ float apply(float x, float c) {
+  if constexpr (OP == kNull) return x;
+  else if constexpr (OP == kUnit) {
+#pragma unroll
+    for (int r = 0; r < kUnitOps; ++r) x = fmaf(x, c, 0.25f);
+    return x;
+  }
+  else if constexpr (OP == kOpAdd) return x + c;
+  else if constexpr (OP == kOpSub) return x - c;
+  else if constexpr (OP == kOpMul) return x * c;
+  else if constexpr (OP == kOpDiv) return fabsf(x) < kDivTau ? 1.0f : c / x;
   else if constexpr (OP == kOpSin) return sinf(x);
   else if constexpr (OP == kOpCos) return cosf(x);
   else if constexpr (OP == kOpTanh) return tanhf(x);
   else if constexpr (OP == kOpExp) {
-    const float c = x > kExpClamp ? kExpClamp : (x < -kExpClamp ? -kExpClamp : x);
-    return expf(c) - y;                                                                 // one extra sub
+    const float e = x > kExpClamp ? kExpClamp : (x < -kExpClamp ? -kExpClamp : x);
+    return expf(e);
   } else if constexpr (OP == kOpLog) return logf(fabsf(x) + kLogEps);
-  else if constexpr (OP == kOpMax) return fmaxf(x, y);
-  else if constexpr (OP == kOpMin) return fminf(x, y);
-  else return tanf(x) * y;                                                              // one extra mul
+  else if constexpr (OP == kOpMax) return fmaxf(x, c);
+  else if constexpr (OP == kOpMin) return fminf(x, c);
+  else return tanf(x);
 }
 
 template <int OP>
-__global__ __launch_bounds__(256) void opcost_kernel(float* out, int iters, float y) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  float x[8];
+__global__ __launch_bounds__(256) void opcost_kernel(float* out, int iters, float c, float scale) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t u[8];
+  float acc[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) x[k] = 0.5f + 0.01f * (float)((t + k) & 63);
+  for (int k = 0; k < 8; ++k) {
+    u[k] = (t * 8u + (uint32_t)k) * 2654435761u;
+    acc[k] = 0.0f;
+  }
   for (int i = 0; i < iters; ++i) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = step<OP>(x[k], y);
+    for (int k = 0; k < 8; ++k) {
+      u[k] += 0x9E3779B9u;
+      const float x = (float)(int32_t)u[k] * scale;
+      acc[k] += apply<OP>(x, c);
+    }
   }
   float s = 0.0f;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) s += x[k];
+  for (int k = 0; k < 8; ++k) s += acc[k];
   out[t] = s;
 }
 
@@ -85,39 +110,49 @@ using namespace tgp;
 
 extern "C" {
 
-__attribute__((visibility("default"))) tgp_status tgp_op_rate(int32_t op, double* ops_per_s) {
-  if (!ops_per_s || op < 0 || op >= kNumOps) return TGP_E_ARG;
-  const int threads = 256, blocks = 4096, iters = 2048;
+__attribute__((visibility("default"))) tgp_status tgp_op_cost(int32_t op, double* slots) {
+  if (!slots || op < 0 || op >= kNumOps) return TGP_E_ARG;
+  const int threads = 256, blocks = 4096, iters = 512;
   float* out = nullptr;
   if (hipMalloc(&out, sizeof(float) * threads * blocks) != hipSuccess) return TGP_E_HIP;
   hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  auto launch = [&](hipStream_t s) {
-    switch (op) {
-#define TGP_OPC(O) case O: opcost_kernel<O><<<blocks, threads, 0, s>>>(out, iters, O == kOpDiv ? 1.3f : (O == kOpMul ? 0.99999f : (O == kOpExp ? 1.5f : (O == kOpTan ? 0.25f : 0.001f)))); break;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    hipFree(out);
+    return TGP_E_HIP;
+  }
+  // input ranges: [-20, 20) for exp (its clamp range), [-8, 8) otherwise
+  const float two31 = 4.656612873e-10f;  // 2^-31
+  auto launch = [&](int which) {
+    const float scale = (which == kOpExp ? 20.0f : 8.0f) * two31;
+    switch (which) {
+#define TGP_OPC(O) case O: opcost_kernel<O><<<blocks, threads, 0, 0>>>(out, iters, 0.75f, scale); break;
+      TGP_OPC(kNull) TGP_OPC(kUnit)
       TGP_OPC(0) TGP_OPC(1) TGP_OPC(2) TGP_OPC(3) TGP_OPC(4) TGP_OPC(5)
       TGP_OPC(6) TGP_OPC(7) TGP_OPC(8) TGP_OPC(9) TGP_OPC(10) TGP_OPC(11)
 #undef TGP_OPC
     }
   };
-  launch(0);  // warm-up
-  float best = 1e30f;
-  for (int r = 0; r < 3; ++r) {
-    hipEventRecord(e0, 0);
-    launch(0);
-    hipEventRecord(e1, 0);
-    hipEventSynchronize(e1);
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    best = ms < best ? ms : best;
-  }
+  auto best_ms = [&](int which) {
+    launch(which);  // warm-up
+    float best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      hipEventRecord(e0, 0);
+      launch(which);
+      hipEventRecord(e1, 0);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      best = ms < best ? ms : best;
+    }
+    return (double)best;
+  };
+  const double t_null = best_ms(kNull), t_unit = best_ms(kUnit), t_op = best_ms(op);
   const hipError_t err = hipGetLastError();
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(out);
   if (err != hipSuccess) return TGP_E_HIP;
-  *ops_per_s = (double)threads * blocks * iters * 8 / (best * 1e-3);
+  *slots = (t_op - t_null) / ((t_unit - t_null) / kUnitOps);
   return TGP_OK;
 }
 

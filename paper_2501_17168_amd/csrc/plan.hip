@@ -48,7 +48,7 @@ constexpr int kRecPop = 1 << 20;
 __device__ __forceinline__ bool is_intf(float x) { return isfinite(x) && x == floorf(x); }
 
 __device__ __forceinline__ bool fused_op(int op) {
-  return op == kOpAdd || op == kOpSub || op == kOpMul || op == kOpMax || op == kOpMin;
+  return op == kOpAdd || op == kOpSub || op == kOpMul || op == kOpDiv || op == kOpMax || op == kOpMin;
 }
 
 // number of instructions a function node emits for its own operation
@@ -102,6 +102,7 @@ __device__ __forceinline__ int fused_case(int op, bool a_first, int src) {
     case kOpMul: return kMUL + src;
     case kOpMax: return kMAX + src;
     case kOpMin: return kMIN + src;
+    case kOpDiv: return (a_first ? kDIVA : kDIVR) + src;
     default: return (a_first ? kSUBA : kSUBR) + src;  // kOpSub
   }
 }

@@ -59,7 +59,9 @@ constexpr int kMAX = kMUL + kNumSrc;      // A = max(A, src)
 constexpr int kMIN = kMAX + kNumSrc;      // A = min(A, src)
 constexpr int kSUBA = kMIN + kNumSrc;     // A = A - src
 constexpr int kSUBR = kSUBA + kNumSrc;    // A = src - A
-constexpr int kSPL = kSUBR + kNumSrc;     // R[k] = A, k < 4
+constexpr int kDIVA = kSUBR + kNumSrc;    // A = A / src (protected)
+constexpr int kDIVR = kDIVA + kNumSrc;    // A = src / A (protected)
+constexpr int kSPL = kDIVR + kNumSrc;     // R[k] = A, k < 4
 constexpr int kSPLM = kSPL + kRegSlots;   // LDS slot aux = A
 constexpr int kTA = kSPLM + 1;            // T = A
 constexpr int kBT = kTA + 1;              // A = op(A,T) (ord 0) or op(T,A) (ord 1): kBT + 2*bin_index + ord
