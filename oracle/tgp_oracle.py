@@ -359,8 +359,39 @@ def apply_op_shadow32(op, a, b=None):
         return _r32(apply_op(op, a, b))
 
 
-def eval_shadow32(d, X, n_out):
-    """Float32 shadow evaluation (same order as eval_stack)."""
+# Unary transcendental ops: sin, cos, tanh, exp, log, tan. A float32 library
+# implementation of these may differ from the correctly rounded result by a
+# few ulp, so classification shadows may move their results by a random
+# number of ulps (see Ulps).
+TRANSCENDENTAL = frozenset((4, 5, 6, 7, 8, 11))
+
+
+class Ulps:
+    """Random perturbation of transcendental results in the float32 shadow:
+    each result (per node and point) moves by an integer number of float32
+    ulps drawn uniformly from [-k, k], from a generator seeded by `seed`."""
+
+    def __init__(self, k, seed):
+        self.k = int(k)
+        self.rng = np.random.default_rng(seed)
+
+    def __call__(self, op, r):
+        if self.k <= 0 or op not in TRANSCENDENTAL:
+            return r
+        r32 = np.asarray(r, np.float64).astype(np.float32)
+        steps = self.rng.integers(-self.k, self.k + 1, size=r32.shape)
+        out = r32.copy()
+        for direction, sel in ((np.float32(np.inf), steps > 0), (np.float32(-np.inf), steps < 0)):
+            cur = r32.copy()
+            for n in range(1, self.k + 1):
+                cur = np.nextafter(cur, direction)
+                out = np.where(sel & (np.abs(steps) == n), cur, out)
+        return out.astype(np.float64)
+
+
+def eval_shadow32(d, X, n_out, ulps=None):
+    """Float32 shadow evaluation (same order as eval_stack). With `ulps` (an
+    Ulps), transcendental results are perturbed as a library might round."""
     X = _r32(X)
     D = X.shape[1]
     stack = []
@@ -376,6 +407,8 @@ def eval_shadow32(d, X, n_out):
         else:
             a = stack.pop()
             r = apply_op_shadow32(op, a); right = a
+        if ulps is not None:
+            r = ulps(op, r)
         if d.out[i] >= 0:
             contrib[i] = (d.out[i], r)
             stack.append(right)
@@ -409,12 +442,12 @@ def mse_tree(d, X, Y, n_out, evaluator=eval_stack):
         return float(np.sum(e * e) / D)
 
 
-def mse_tree_shadow32(d, X, Y, n_out):
+def mse_tree_shadow32(d, X, Y, n_out, ulps=None):
     """Shadow fitness: float32 residuals and squares, float64 sum, float32 result."""
     if d.status != OK:
         return float("nan")
     D = np.asarray(X).shape[1]
-    out = eval_shadow32(d, X, n_out)
+    out = eval_shadow32(d, X, n_out, ulps)
     with np.errstate(all="ignore"):
         e = _r32(out - _r32(_Y(Y, n_out, D)))
         e2 = _r32(e * e)
@@ -430,12 +463,15 @@ def mse(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, evaluator=eval_
                               evaluator) for p in rows])
 
 
-def mse_shadow32(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None):
+def mse_shadow32(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, ulp=0, seed=0):
+    """Float32 shadow fitness per tree; ulp > 0 perturbs transcendental results
+    by up to `ulp` float32 ulps (one generator seeded by `seed` for the call)."""
     X = np.asarray(X)
     V = X.shape[0]
     rows = range(pop_type.shape[0]) if rows is None else rows
-    return np.array([mse_tree_shadow32(decode(pop_type[p], pop_value[p], pop_size[p], V, n_out), X, Y, n_out)
-                     for p in rows])
+    ulps = Ulps(ulp, seed) if ulp else None
+    return np.array([mse_tree_shadow32(decode(pop_type[p], pop_value[p], pop_size[p], V, n_out), X, Y, n_out,
+                                       ulps) for p in rows])
 
 
 def predict(pop_type, pop_value, pop_size, X, n_out=1, rows=None):
@@ -452,7 +488,7 @@ def predict(pop_type, pop_value, pop_size, X, n_out=1, rows=None):
 
 
 # ---------------------------------------------------------------- gradients
-def grad_tree(d, X, Y, n_out, g=1.0, shadow=False):
+def grad_tree(d, X, Y, n_out, g=1.0, shadow=False, ulps=None):
     """Reverse-mode gradient of g * fitness for one tree, with a full tape.
 
     Returns (mse, grad_value [len], grad_X [V][D]). grad_value is non-zero
@@ -468,7 +504,11 @@ def grad_tree(d, X, Y, n_out, g=1.0, shadow=False):
     classifies gradient components as well- or ill-conditioned.
     """
     q = _r32 if shadow else (lambda v: v)
-    op_val = apply_op_shadow32 if shadow else apply_op
+    if shadow and ulps is not None:
+        def op_val(op, a, b=None):
+            return ulps(op, apply_op_shadow32(op, a, b))
+    else:
+        op_val = apply_op_shadow32 if shadow else apply_op
     X = q(np.asarray(X, np.float64))
     V, D = X.shape
     n = d.length
@@ -532,12 +572,13 @@ def grad_tree(d, X, Y, n_out, g=1.0, shadow=False):
     return m, gv, gX
 
 
-def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, shadow=False):
+def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, shadow=False, ulp=0, seed=0):
     """Gradients of sum_t g_t * fitness_t.
 
     Returns (mse [R], grad_value [R][Lmax] (zero off constant nodes, zero for
     invalid trees), grad_X [V][D] summed over the listed trees). shadow=True
-    gives the float32 shadow of the same gradients (see grad_tree)."""
+    gives the float32 shadow of the same gradients (see grad_tree); ulp > 0
+    also perturbs its transcendental node values (see Ulps)."""
     X = np.asarray(X, np.float64)
     V, D = X.shape
     rows = list(range(pop_type.shape[0]) if rows is None else rows)
@@ -545,12 +586,13 @@ def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, shadow
     m = np.full(len(rows), np.nan)
     gv = np.zeros((len(rows), Lmax))
     gX = np.zeros((V, D))
+    ulps = Ulps(ulp, seed) if (shadow and ulp) else None
     for k, p in enumerate(rows):
         d = decode(pop_type[p], pop_value[p], pop_size[p], V, n_out)
         if d.status != OK:
             continue
         gt = 1.0 if g is None else float(g[p])
-        m[k], gvt, gXt = grad_tree(d, X, Y, n_out, gt, shadow=shadow)
+        m[k], gvt, gXt = grad_tree(d, X, Y, n_out, gt, shadow=shadow, ulps=ulps)
         gv[k, :d.length] = gvt
         gX += gXt
     return m, gv, gX

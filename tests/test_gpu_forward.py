@@ -9,7 +9,7 @@ import oracle as O
 import paper_2501_17168_amd as tgp
 import synth
 from golden_io import load_tree
-from parity import compare_fitness
+from parity import shadows, compare_fitness
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -36,7 +36,7 @@ def to_dev(w, Y):
 
 def oracle_fit(w, Y, rows=None):
     m64 = O.mse(w.type, w.value, w.size, w.X, Y, w.n_out, rows=rows)
-    m32 = O.mse_shadow32(w.type, w.value, w.size, w.X, Y, w.n_out, rows=rows)
+    m32 = shadows(w.type, w.value, w.size, w.X, Y, w.n_out, rows=rows)
     return m64, m32
 
 
@@ -113,10 +113,10 @@ def test_invalid_trees_status_and_nan():
     m = tgp.eval_mse(pop, torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV), tree_status=stt).cpu().numpy()
     np.testing.assert_array_equal(stt.cpu().numpy(), ref[:, 0])
     m64 = O.mse(T, Vv, S, X, Y)
-    m32 = O.mse_shadow32(T, Vv, S, X, Y)
+    m32 = shadows(T, Vv, S, X, Y)
     valid = ref[:, 0] == 0
     assert np.isnan(m[~valid]).all()
-    compare_fitness(m[valid], m64[valid], m32[valid], label="valid rows of the fault list")
+    compare_fitness(m[valid], m64[valid], m32[:, valid], label="valid rows of the fault list")
 
 
 MODES = [("tree", dict(mode=1)), ("tree-bw1", dict(mode=1, block_waves=1)), ("point", dict(mode=2)),
@@ -227,7 +227,7 @@ def test_edge_shapes(K):
             got = device_fit(pop, torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV), 1,
                              tgp.cfg(mode=mode, points_per_lane=K))
             m64 = O.mse(T, Vv, S, X, Y)
-            m32 = O.mse_shadow32(T, Vv, S, X, Y)
+            m32 = shadows(T, Vv, S, X, Y)
             compare_fitness(got, m64, m32, max_ill_mismatch=0.0, label=f"D={D} mode={mode}")
 
 

@@ -8,7 +8,8 @@ import torch
 import oracle as O
 import paper_2501_17168_amd as tgp
 import synth
-from parity import classify, compare_fitness
+from parity import shadows, classify, compare_fitness, grad_shadows, well_grad
+from parity import grad_close as _grad_close
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -29,12 +30,7 @@ def dev_pop(w):
 
 
 def grad_close(g, ref, rel=1e-3):
-    """|g - ref| <= rel * max(|ref|, 1e-3 * max|ref| of the row) + 1e-7, elementwise, per row."""
-    g = np.asarray(g, np.float64)
-    ref = np.asarray(ref, np.float64)
-    scale = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref), axis=-1, keepdims=True))
-    with np.errstate(invalid="ignore"):
-        return np.abs(g - ref) <= rel * scale + 1e-7
+    return _grad_close(g, ref, rel)
 
 
 @pytest.mark.parametrize("name,P,D", [("grad", 400, 3100), ("hybrid", 300, 2000), ("plain", None, None)])
@@ -44,7 +40,7 @@ def test_grad_matches_oracle(name, P, D):
     X = torch.from_numpy(w.X).to(DEV)
     Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
     m64 = O.mse(w.type, w.value, w.size, w.X, Y)
-    m32 = O.mse_shadow32(w.type, w.value, w.size, w.X, Y)
+    m32 = shadows(w.type, w.value, w.size, w.X, Y)
     well, _ = classify(m64, m32)
     # only well-conditioned trees feed the X gradient: their upstream weight is 1, the others' 0
     gw = np.where(well, 1.0, 0.0).astype(np.float32)
@@ -53,14 +49,14 @@ def test_grad_matches_oracle(name, P, D):
     compare_fitness(mse.cpu().numpy(), m64, m32, label=f"{name} fitness from the gradient call")
     rows = np.nonzero(well)[0]
     _, gv64, gx64 = O.grad(w.type, w.value, w.size, w.X, Y, rows=rows)
-    _, gv32, gx32 = O.grad(w.type, w.value, w.size, w.X, Y, rows=rows, shadow=True)
     gvd = gv.cpu().numpy()[rows]
     const = w.type[rows] == 1
-    # a component is well-conditioned when the float32 shadow of the sweep
+    # a component is well-conditioned when every float32 shadow of the sweep
     # agrees with float64 to a tenth of the tolerance; near-singular
     # quotients under bounded functions make a few components depend on
     # float32 rounding even in trees whose fitness does not
-    wellg = grad_close(gv32, gv64, rel=1e-4) & const
+    wv, wellx = well_grad(grad_shadows(w.type, w.value, w.size, w.X, Y, rows=rows), gv64, gx64)
+    wellg = wv & const
     ok = grad_close(gvd, gv64) | ~wellg
     frac_bad = 1.0 - ok[wellg].mean()
     print(f"{name}: {wellg.sum()} well-conditioned constant gradients, {(const & ~wellg).sum()} ill-conditioned; "
@@ -69,7 +65,6 @@ def test_grad_matches_oracle(name, P, D):
     assert frac_bad <= 0.005, (name, frac_bad, np.argwhere(~ok)[:5])
     assert (gvd[~const] == 0).all()
     gxd = gx.cpu().numpy()
-    wellx = grad_close(gx32, gx64, rel=2e-4)
     okx = grad_close(gxd, gx64, rel=2e-3) | ~wellx
     assert wellx.mean() >= 0.9
     assert okx.mean() >= 0.995, (name, 1 - okx.mean())
@@ -83,16 +78,16 @@ def test_grad_vs_finite_differences():
     _, gv, _ = tgp.eval_mse_grad(pop, X, Yd)
     gv = gv.cpu().numpy()
     m64 = O.mse(w.type, w.value, w.size, w.X, Y)
-    m32 = O.mse_shadow32(w.type, w.value, w.size, w.X, Y)
+    m32 = shadows(w.type, w.value, w.size, w.X, Y)
     well, _ = classify(m64, m32)
     rng = np.random.default_rng(0)
     cand = [p for p in np.nonzero(well & ((w.type == 1).sum(1) > 0) & (m64 < 1e4))[0]]
     checked = agree = 0
     for p in rng.choice(cand, size=min(100, len(cand)), replace=False):
         i = int(rng.choice(np.nonzero(w.type[p] == 1)[0]))
-        _, g64, _ = O.grad(w.type, w.value, w.size, w.X, Y, rows=[p])
-        _, g32, _ = O.grad(w.type, w.value, w.size, w.X, Y, rows=[p], shadow=True)
-        if not grad_close(g32[0, i:i + 1], g64[0, i:i + 1], rel=1e-4)[0]:
+        _, g64, gx64 = O.grad(w.type, w.value, w.size, w.X, Y, rows=[p])
+        wv, _ = well_grad(grad_shadows(w.type, w.value, w.size, w.X, Y, rows=[p]), g64, gx64)
+        if not wv[0, i]:
             continue   # float32-sensitive component
         f1 = O.fd_grad_const(w.type, w.value, w.size, w.X, Y, p, i, h=1e-4)
         f2 = O.fd_grad_const(w.type, w.value, w.size, w.X, Y, p, i, h=2.5e-5)

@@ -418,6 +418,38 @@ def test_gradient_shadow_close_on_random_trees():
     assert close[const].mean() > 0.9
 
 
+def test_shadow_ulp_perturbation():
+    # SIN(x0): the perturbed shadow moves each point by an integer number of
+    # float32 ulps in [-2, 2], each step count occurring; without
+    # transcendental nodes nothing moves
+    t, v, s = _rows([(2, 4, 2), (0, 0, 1)], 8)
+    d = O.decode(t, v, s, 1, 1)
+    X = rng0.uniform(-3, 3, size=(1, 4000))
+    base = O.eval_shadow32(d, X, 1)[0].astype(np.float32)
+    pert = O.eval_shadow32(d, X, 1, ulps=O.Ulps(2, 7))[0].astype(np.float32)
+    steps = np.zeros(base.shape, np.int64)
+    for k in (1, 2):
+        up, dn = base.copy(), base.copy()
+        for _ in range(k):
+            up = np.nextafter(up, np.float32(np.inf))
+            dn = np.nextafter(dn, np.float32(-np.inf))
+        steps[pert == up] = k
+        steps[pert == dn] = -k
+    moved = pert != base
+    assert np.all(moved == (steps != 0))
+    assert set(np.unique(steps).tolist()) == {-2, -1, 0, 1, 2}
+    assert 0.7 < moved.mean() < 0.9
+    # + - * / only: identical
+    t, v, s = _rows([(2, 3, 5), (2, 0, 3), (0, 0, 1), (1, 0.5, 1), (0, 0, 1)], 8)
+    d = O.decode(t, v, s, 1, 1)
+    np.testing.assert_array_equal(O.eval_shadow32(d, X, 1), O.eval_shadow32(d, X, 1, ulps=O.Ulps(2, 3)))
+    # fitness: ulp=0 is the plain shadow
+    w = synth.workload("hybrid", P=30, D=64)
+    Y = w.targets_from(O.predict(*w.hidden, w.X, 1)[:, 0, :])
+    np.testing.assert_array_equal(O.mse_shadow32(w.type, w.value, w.size, w.X, Y),
+                                  O.mse_shadow32(w.type, w.value, w.size, w.X, Y, ulp=0, seed=5))
+
+
 def test_adam_reference_matches_torch():
     torch = pytest.importorskip("torch")
     A = np.diag([1.0, 3.0, 0.5])
