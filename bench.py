@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-forward / batched-persistent graph / forward+adjoint comparison")
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed steps, copy this many MiB device to device once: a kernel of known "
+                         "traffic for calibrating memory counters")
     return ap.parse_args()
 
 
@@ -273,6 +276,14 @@ def main():
     _lib.profile(False)
     ms_step = ms / args.steps
     value = gpops_per_step * args.steps / (ms * 1e-3)
+
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
 
