@@ -95,7 +95,13 @@ typedef struct tgp_data {
  * the built-in default". */
 enum { TGP_MODE_AUTO = 0, TGP_MODE_TREE_MAJOR = 1, TGP_MODE_POINT_MAJOR = 2,
        TGP_MODE_PERSISTENT = 3 };
-enum { TGP_FLAG_NO_TAIL_CHECK = 1 };   /* skip reading the NaN padding after len */
+/* Persistent mode: trees are ordered longest length bucket first; the waves
+ * bound to each point tile take that order in chunks of trees_per_unit,
+ * pulled from the tile's queue (one atomic per chunk, on up to 8 counters
+ * per tile) or, with TGP_FLAG_STATIC_ORDER, dealt round-robin in snake
+ * order without atomics. */
+enum { TGP_FLAG_NO_TAIL_CHECK = 1,     /* skip reading the NaN padding after len */
+       TGP_FLAG_STATIC_ORDER = 2 };
 typedef struct tgp_cfg {
   int32_t mode;             /* TGP_MODE_*                                           */
   int32_t block_waves;      /* waves per workgroup: 1, 2 or 4                       */

@@ -21,7 +21,7 @@ using namespace tgp;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kCounters = 64 + kMaxQueues * kQueueStride;  // hist[16] | cursor[17] @16 | queues @64
+constexpr int kCounters = 64 + kMaxTileQueues * kQueueStride;  // hist[16] | cursor[17] @16 | tile queues @64
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -49,7 +49,7 @@ tgp_status check_pop(const tgp_pop* pop) {
   if (pop->Lmax < 1) return TGP_E_SHAPE;
   if (pop->Lmax > kMaxLmax) return TGP_E_UNSUPPORTED;
   if (pop->row_stride < pop->Lmax) return TGP_E_SHAPE;
-  if (pop->P > (int64_t)INT32_MAX) return TGP_E_UNSUPPORTED;
+  if (pop->P > (int64_t)kHdrTree) return TGP_E_UNSUPPORTED;  // tree index in a 30-bit header field
   return TGP_OK;
 }
 
@@ -107,6 +107,8 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
   const int64_t ntiles = (d->D + tile - 1) / tile;
   if (c.mode < TGP_MODE_TREE_MAJOR || c.mode > TGP_MODE_PERSISTENT)
     c.mode = d->D > 16384 ? TGP_MODE_POINT_MAJOR : TGP_MODE_TREE_MAJOR;
+  // persistent waves are bound to tiles, one queue per tile
+  if (c.mode == TGP_MODE_PERSISTENT && ntiles > kMaxTileQueues) c.mode = TGP_MODE_POINT_MAJOR;
   if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4)
     c.block_waves = (int)std::min<int64_t>(4, std::max<int64_t>(1, ntiles));
   if (c.trees_per_unit < 1) {
@@ -138,9 +140,9 @@ int device_cus() {
 // Enqueue prep + plan (+ order). Returns the plan-related pointers.
 tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
                         const Layout& L, int32_t* out_info, int32_t* out_status, bool want_order,
-                        hipStream_t s, bool want_adj = false) {
+                        hipStream_t s, bool want_adj = false, int64_t n_queues = 0) {
   int32_t* counters = (int32_t*)(ws + L.counters);
-  if (launch_prep(counters, kCounters, s) != hipSuccess) return TGP_E_HIP;
+  if (launch_prep(counters, (int)(64 + n_queues * kQueueStride), s) != hipSuccess) return TGP_E_HIP;
   PlanArgs pa{};
   pa.type = pop->type;
   pa.value = pop->value;
@@ -185,12 +187,14 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   if (pop->P == 0) return TGP_OK;
   const tgp_cfg c = resolve(cfg, pop, d, n_out, false);
   char* w = (char*)ws;
-  st = enqueue_plan(pop, d->V, n_out, c, w, L, nullptr, nullptr, c.mode == TGP_MODE_PERSISTENT, s);
-  if (st) return st;
-
   const int K = c.points_per_lane;
   const int64_t tile = 64LL * K;
   const int64_t ntiles = (d->D + tile - 1) / tile;
+  const bool persistent = c.mode == TGP_MODE_PERSISTENT;
+  st = enqueue_plan(pop, d->V, n_out, c, w, L, nullptr, nullptr, persistent, s, false,
+                    (persistent && !(c.flags & TGP_FLAG_STATIC_ORDER)) ? kMaxTileQueues : 0);
+  if (st) return st;
+
   const int bw = c.block_waves;
   EvalArgs ea{};
   ea.X = d->X;
@@ -219,10 +223,15 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   } else if (c.mode == TGP_MODE_POINT_MAJOR) {
     grid = ((pop->P + ea.tpu - 1) / ea.tpu) * ea.ngroups;
   } else {
-    ea.n_units = ((pop->P + ea.tpu - 1) / ea.tpu) * ntiles;
-    const int64_t waves = (int64_t)device_cus() * 12;  // resident waves the kernel can hold
-    grid = std::max<int64_t>(1, std::min<int64_t>((ea.n_units + bw - 1) / bw, waves / bw));
-    ea.nq = (int32_t)std::min<int64_t>(kMaxQueues, grid);
+    // resident waves per CU the kernel can hold (4 SIMDs x its occupancy by K)
+    const int per_cu = K >= 16 ? 8 : (K >= 8 ? 12 : 20);
+    const int64_t cap = (int64_t)device_cus() * per_cu;
+    const int64_t chunks = (pop->P + ea.tpu - 1) / ea.tpu;
+    ea.wpt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap / ntiles, chunks));
+    ea.dynamic = (c.flags & TGP_FLAG_STATIC_ORDER) ? 0 : 1;
+    // up to 8 sub-queues per tile, each served by at least one wave
+    ea.nsub = (int32_t)std::max<int64_t>(1, std::min<int64_t>({8, kMaxTileQueues / ntiles, (int64_t)ea.wpt}));
+    grid = (ntiles * ea.wpt + bw - 1) / bw;
   }
   const int NO = (n_out > 1) ? kMaxOut : 1;
   void* tok = nullptr;

@@ -60,7 +60,9 @@ tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, tgp_cf
     for (int bw : {1, 2, 4}) cands.push_back(tgp_cfg{TGP_MODE_TREE_MAJOR, bw, k, 1, 0});
     for (int tpu : {1, 4, 16, 64})
       cands.push_back(tgp_cfg{TGP_MODE_POINT_MAJOR, 4, k, tpu, 0});
-    for (int tpu : {1, 4, 16}) cands.push_back(tgp_cfg{TGP_MODE_PERSISTENT, 4, k, tpu, 0});
+    for (int bw : {1, 4})
+      for (int tpu : {1, 2, 4}) cands.push_back(tgp_cfg{TGP_MODE_PERSISTENT, bw, k, tpu, 0});
+    cands.push_back(tgp_cfg{TGP_MODE_PERSISTENT, 4, k, 1, TGP_FLAG_STATIC_ORDER});
   }
   tgp_cfg best{};
   float best_ms = 1e30f;

@@ -14,12 +14,20 @@
 //
 // Work units: tree-major gives each workgroup one tree and block_waves
 // consecutive tiles; point-major gives each workgroup block_waves tiles and
-// a run of trees, loading the X tile once; persistent waves pull
-// (tree chunk, tile) units from a counter, with trees ordered longest
-// length bucket first.
+// a run of trees; persistent waves are bound to one tile each and pull
+// chunks of trees, longest length bucket first, from that tile's queue.
+// A wave loads its tile of X and Y once per unit (once per life in the
+// persistent schedule) and keeps it in registers.
 //
-// Reduction: per lane, float32 residual and square, float64 sum over its K
-// points; float64 wave reduction; one float64 atomic per (wave, tree).
+// Latency: while one tree runs, the wave already has the header of the
+// next one and is loading the one after; the next tree's first program
+// word is requested before the current tree's reduction. These prefetches
+// are vector loads (broadcast of one address), whose in-order completion
+// lets them stay in flight across the interpreter's scalar-load waits;
+// the persistent queue's next chunk is requested one chunk ahead.
+//
+// Reduction: per lane, float32 residual and square; pairwise lane sum and
+// DPP wave sum in float32; one float64 atomic per (wave, tree).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -46,20 +54,30 @@ __device__ __forceinline__ float lane_sum_sq(const float (&sq)[K]) {
   return t[0];
 }
 
+// The wave's point tile: X in the interpreter registers, Y beside it.
+template <int K, int NO>
+struct TileY {
+  float y[NO][K];
+};
+
 template <int K, int VM, int NO>
-__device__ __forceinline__ void load_x(const EvalArgs& a, Regs<K, VM, NO>& s, int64_t p0) {
+__device__ __forceinline__ void load_tile(const EvalArgs& a, Regs<K, VM, NO>& s, TileY<K, NO>& ty, int64_t p0) {
 #pragma unroll
   for (int v = 0; v < VM; ++v) {
-    if (v < a.V) {
-      const float* xr = a.X + (int64_t)v * a.ldx;
+    const float* xr = a.X + (int64_t)(v < a.V ? v : 0) * a.ldx;
 #pragma unroll
-      for (int j = 0; j < K; ++j) {
-        const int64_t p = p0 + j * kWave;
-        s.X[v][j] = p < a.D ? xr[p] : 0.0f;
-      }
-    } else {
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = p0 + j * kWave;
+      s.X[v][j] = (v < a.V && p < a.D) ? xr[p] : 0.0f;
+    }
+  }
 #pragma unroll
-      for (int j = 0; j < K; ++j) s.X[v][j] = 0.0f;
+  for (int o = 0; o < NO; ++o) {
+    const float* yr = a.Y ? a.Y + (int64_t)(o < a.n_out ? o : 0) * a.ldy : nullptr;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = p0 + j * kWave;
+      ty.y[o][j] = (yr && o < a.n_out && p < a.D) ? yr[p] : 0.0f;
     }
   }
 }
@@ -67,23 +85,35 @@ __device__ __forceinline__ void load_x(const EvalArgs& a, Regs<K, VM, NO>& s, in
 // Output o of the tree at point slot j: a tree without Modi nodes predicts
 // (root, 0, ..., 0); the root value is the accumulator A.
 template <int K, int VM, int NO>
-__device__ __forceinline__ float out_val(const Regs<K, VM, NO>& s, int nmodi, int o, int j) {
-  return nmodi ? s.O[o][j] : (o == 0 ? s.A[j] : 0.0f);
+__device__ __forceinline__ float out_val(const Regs<K, VM, NO>& s, bool modi, int o, int j) {
+  return modi ? s.O[o][j] : (o == 0 ? s.A[j] : 0.0f);
 }
 
-// Evaluate tree t on the tile whose first point for this lane is p0.
+// Broadcast loads: every lane reads the same address with a vector load;
+// the value is taken from lane 0 when it is needed.
+__device__ __forceinline__ uint32_t bcast_load_u32(const int32_t* p) { return (uint32_t)*p; }
+__device__ __forceinline__ uint2 bcast_load_u64(const uint2* p) { return *p; }
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uniform64(uint2 v) {
+  return (unsigned long long)uniform(v.x) | ((unsigned long long)uniform(v.y) << 32);
+}
+
+// Evaluate the tree with header `hdr` on the tile whose first point for this
+// lane is p0, starting from its already-loaded first program word. Between
+// the program and the reduction, `between()` runs (the next prefetch).
 //
 // Fitness reduction: squared residuals in float32, summed pairwise per lane
 // and over the wave by DPP (all terms non-negative: relative error below
 // (log2 K + 6) float32 ulp, under 6e-7), then added in float64 across
 // waves. If the float32 wave sum overflows, the tile is summed again in
 // float64 (terms that are themselves infinite give the same result).
-template <int K, int VM, int NO, bool PRED>
-__device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, float* spill, int64_t t,
-                                          int64_t p0, int lane) {
-  const int32_t* inf = a.info + t * kInfoStride;
-  const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
-  if (status != 0) {
+template <int K, int VM, int NO, bool PRED, class Between>
+__device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, const TileY<K, NO>& ty,
+                                          float* spill, uint32_t hdr, unsigned long long first, int64_t p0,
+                                          int lane, Between between) {
+  const int64_t t = hdr & kHdrTree;
+  if (hdr & kHdrInvalid) {
+    between();
     if constexpr (PRED) {
       for (int o = 0; o < a.n_out; ++o) {
         float* pr = a.pred + (t * a.n_out + o) * a.ldp;
@@ -96,15 +126,16 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
     }
     return;
   }
-  const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
-  if (nmodi) {
+  const bool modi = (hdr & kHdrModi) != 0;
+  if (modi) {
 #pragma unroll
     for (int q = 0; q < NO; ++q)
 #pragma unroll
       for (int j = 0; j < K; ++j) s.O[q][j] = 0.0f;
   }
   // every program starts by loading A
-  run_program<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), s, spill);
+  run_from<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), first, s, spill);
+  between();
 
   if constexpr (PRED) {
 #pragma unroll
@@ -114,7 +145,7 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int64_t p = p0 + j * kWave;
-          if (p < a.D) pr[p] = out_val(s, nmodi, o, j);
+          if (p < a.D) pr[p] = out_val(s, modi, o, j);
         }
       }
     }
@@ -124,12 +155,11 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     if (o < a.n_out) {
-      const float* yr = a.Y + (int64_t)o * a.ldy;
       float sq[K];
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int64_t p = p0 + j * kWave;
-        const float e = p < a.D ? out_val(s, nmodi, o, j) - yr[p] : 0.0f;
+        const float e = p < a.D ? out_val(s, modi, o, j) - ty.y[o][j] : 0.0f;
         sq[j] = e * e;
       }
       lane_sum += lane_sum_sq<K>(sq);
@@ -142,11 +172,10 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
       if (o < a.n_out) {
-        const float* yr = a.Y + (int64_t)o * a.ldy;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           const int64_t p = p0 + j * kWave;
-          const float e = p < a.D ? out_val(s, nmodi, o, j) - yr[p] : 0.0f;
+          const float e = p < a.D ? out_val(s, modi, o, j) - ty.y[o][j] : 0.0f;
           l64 += (double)(e * e);
         }
       }
@@ -156,6 +185,55 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
   if (lane == 0) unsafeAtomicAdd(&a.acc[t], tot);
 }
 
+// Positions of the trees one wave evaluates on its tile.
+//   contiguous (tree-major, point-major): trees k in [k, kend), header from
+//   the tree record;
+//   persistent: chunks of tpu positions of the length-sorted order. Chunk
+//   numbers come round-robin in snake order (round r gives wave j of the
+//   tile's n waves chunk r n + j, or r n + n - 1 - j on odd rounds, so the
+//   longest chunk of each round goes to a different end and every wave's
+//   total is within about one chunk of the others) or, dynamic, from the
+//   tile's counter, with the pop for the chunk after the current one
+//   always in flight. A tile's chunks are split over nsub interleaved
+//   sub-queues so that no counter is shared by too many waves.
+struct Cursor {
+  int64_t k, kend, P;
+  int tpu;
+  int round, j, n;    // round-robin: round, wave in tile, waves per tile (n = 0: no further chunks)
+  int32_t* q;         // dynamic: this wave's sub-queue counter
+  int sub, nsub;      // dynamic: sub-queue s of a tile hands out chunks s, s + nsub, ...
+  int pending;        // dynamic, lane 0: result of the in-flight pop
+
+  __device__ __forceinline__ int pop_issue(int lane) const {
+    int r = 0;
+    if (lane == 0) r = atomicAdd(q, 1);
+    return r;
+  }
+  __device__ __forceinline__ void enter(int64_t c) {
+    k = c * tpu;
+    kend = min(P, k + tpu);
+    if (k >= P) k = P;
+  }
+  __device__ __forceinline__ int64_t snake() const {
+    return (int64_t)round * n + ((round & 1) ? n - 1 - j : j);
+  }
+  // next position, or P when there is none
+  __device__ __forceinline__ int64_t next(int lane) {
+    if (k + 1 < kend) return ++k;
+    if (q) {
+      const int c = (int)uniform((uint32_t)__shfl(pending, 0, kWave));
+      pending = pop_issue(lane);
+      enter((int64_t)c * nsub + sub);
+    } else if (n > 0) {
+      ++round;
+      enter(snake());
+    } else {
+      k = P;
+    }
+    return k;
+  }
+};
+
 }  // namespace
 
 template <int K, int VM, int NO, bool PRED>
@@ -163,48 +241,82 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
   // per wave: LDS spill slots 4..7
   extern __shared__ float s_lds[];
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int W = blockDim.x / kWave;
   float* spill = s_lds + wv * (kLdsFloatsPerWave<K>) + lane;
   Regs<K, VM, NO> s;
+  TileY<K, NO> ty;
   constexpr int kTile = K * kWave;
   const bool persistent = a.mode == TGP_MODE_PERSISTENT;
 
-  int cur_tile = -1;
-  for (int iter = 0;; ++iter) {
-    // ---- next work unit: a point tile and a run [t0, t1) of tree slots ----
-    int tile;
-    int64_t t0, t1;
-    if (persistent) {
-      // queue j hands out units j, j + nq, j + 2 nq, ... in order (longest trees first)
-      const int j = (int)(blockIdx.x % (unsigned)a.nq);
-      int k = 0;
-      if (lane == 0) k = atomicAdd(a.queue + j * kQueueStride, 1);
-      k = __builtin_amdgcn_readfirstlane(__shfl(k, 0, kWave));
-      const int64_t u = (int64_t)j + (int64_t)a.nq * k;
-      if (u >= a.n_units) break;
-      tile = (int)(u % a.ntiles);
-      t0 = (int64_t)(u / a.ntiles) * a.tpu;
-      t1 = min(a.P, t0 + a.tpu);
+  // ---- this wave's tile and first position ----
+  int tile;
+  Cursor cur;
+  cur.P = a.P;
+  cur.tpu = a.tpu;
+  cur.pending = 0;
+  cur.q = nullptr;
+  cur.n = 0;
+  if (persistent) {
+    const int64_t gw = (int64_t)blockIdx.x * W + wv;
+    if (gw >= (int64_t)a.ntiles * a.wpt) return;
+    tile = (int)(gw % a.ntiles);
+    if (a.dynamic) {
+      cur.nsub = a.nsub;
+      cur.sub = (int)((gw / a.ntiles) % a.nsub);
+      cur.q = a.queue + ((int64_t)tile * a.nsub + cur.sub) * kQueueStride;
+      const int c0 = (int)uniform((uint32_t)__shfl(cur.pop_issue(lane), 0, kWave));
+      cur.pending = cur.pop_issue(lane);
+      cur.enter((int64_t)c0 * cur.nsub + cur.sub);
     } else {
-      if (iter > 0) break;
-      const int64_t b = blockIdx.x;
-      const int g = (int)(b % a.ngroups);
-      tile = g * W + wv;
-      t0 = (b / a.ngroups) * a.tpu;
-      t1 = min(a.P, t0 + a.tpu);
-      if (tile >= a.ntiles) break;
+      cur.n = a.wpt;
+      cur.j = (int)(gw / a.ntiles);
+      cur.round = 0;
+      cur.enter(cur.snake());
     }
-    const int64_t p0 = (int64_t)tile * kTile + lane;
-    if (tile != cur_tile) {
-      load_x<K, VM, NO>(a, s, p0);
-      cur_tile = tile;
-    }
-    for (int64_t k = t0; k < t1; ++k) {
-      const int64_t t = persistent ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[k]) : k;
-      if (t < 0 || t >= a.P) continue;
-      eval_tree<K, VM, NO, PRED>(a, s, spill, t, p0, lane);
-    }
+    if (cur.k >= a.P) return;
+  } else {
+    const int64_t b = blockIdx.x;
+    const int g = (int)(b % a.ngroups);
+    tile = g * W + wv;
+    if (tile >= a.ntiles) return;
+    cur.enter(b / a.ngroups);
+    if (cur.k >= a.P) return;
+  }
+  const int64_t p0 = (int64_t)tile * kTile + lane;
+  load_tile<K, VM, NO>(a, s, ty, p0);
+
+  // header of position k: the order entry (queue mode) or the tree record
+  auto hdr_ptr = [&](int64_t k) -> const int32_t* {
+    return persistent ? a.order + k : a.info + k * kInfoStride + kInfoHdr;
+  };
+  auto first_ptr = [&](uint32_t hdr) -> const uint2* {
+    return a.prog + (int64_t)(hdr & kHdrTree) * a.pstride;
+  };
+
+  // pipeline: header of position k1 and first word of its tree are being
+  // loaded (vh1, vf1); header of position k2 is being loaded (vh2)
+  uint32_t hdr = uniform(bcast_load_u32(hdr_ptr(cur.k)));
+  unsigned long long first = 0;
+  if (!(hdr & kHdrInvalid)) first = uniform64(bcast_load_u64(first_ptr(hdr)));
+  int64_t k1 = cur.next(lane);
+  uint32_t vh1 = k1 < a.P ? bcast_load_u32(hdr_ptr(k1)) : kHdrInvalid;
+  for (;;) {
+    const int64_t k2 = k1 < a.P ? cur.next(lane) : a.P;
+    const uint32_t vh2 = k2 < a.P ? bcast_load_u32(hdr_ptr(k2)) : kHdrInvalid;
+    uint32_t h1 = kHdrInvalid;
+    uint2 vf1 = make_uint2(0u, 0u);
+    auto between = [&]() {
+      // the next tree's header has arrived by now; request its first word
+      h1 = k1 < a.P ? uniform(vh1) : kHdrInvalid;
+      if (!(h1 & kHdrInvalid)) vf1 = bcast_load_u64(first_ptr(h1));
+    };
+    eval_tree<K, VM, NO, PRED>(a, s, ty, spill, hdr, first, p0, lane, between);
+    if (k1 >= a.P) break;
+    hdr = h1;
+    first = (h1 & kHdrInvalid) ? 0ull : uniform64(vf1);
+    k1 = k2;
+    vh1 = vh2;
   }
 }
 

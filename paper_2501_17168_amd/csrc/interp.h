@@ -84,10 +84,15 @@ typedef const __attribute__((address_space(4))) unsigned long long* prog_ptr;
 // (at the end of the iteration, not right after issuing it).
 // With BOUNDED, exactly `count` instructions run (a subtree's code range,
 // which has no END of its own); otherwise the program runs up to its END.
+// run_from takes the first instruction word already loaded (`first`, equal
+// to prog[0]); run_program loads it.
 template <int K, int VM, int NO, bool BOUNDED = false>
-__device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, float* spill, int count = 0) {
+__device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first, Regs<K, VM, NO>& s, float* spill,
+                                         int count = 0) {
   if (BOUNDED && count <= 0) return;
-  unsigned long long ins = prog[0];
+  // `first` is wave-uniform; say so, so that it can live in scalar registers
+  unsigned long long ins = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)first) |
+                           ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(first >> 32)) << 32);
   asm volatile("" : "+s"(ins));
   int left = count;
   // one exit (after the latch), so the loop is a single-entry single-exit
@@ -265,6 +270,12 @@ __device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, f
     ins = n2;
     if (act & kActStop) break;
   }
+}
+
+template <int K, int VM, int NO, bool BOUNDED = false>
+__device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, float* spill, int count = 0) {
+  if (BOUNDED && count <= 0) return;
+  run_from<K, VM, NO, BOUNDED>(prog, prog[0], s, spill, count);
 }
 
 // 64-bit DPP move: row_shr / row_bcast as in the GCN data-parallel

@@ -59,18 +59,44 @@ __device__ __forceinline__ int own_code(int r) {
   return 1;
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
-  return v;
+// Wave-wide integer reductions and scans with DPP row shifts and row
+// broadcasts (VALU only; no LDS round trips). All 64 lanes must be active.
+constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROW_MASK, bool KEEP>
+__device__ __forceinline__ int dpp(int v) {
+  // KEEP: lanes without a source keep v; otherwise they read 0
+  return __builtin_amdgcn_update_dpp(KEEP ? v : 0, v, CTRL, ROW_MASK, 0xf, !KEEP);
 }
-__device__ __forceinline__ int wave_max(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));
-  return v;
+
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  x += dpp<kRowShr + 1, 0xf, false>(x);
+  x += dpp<kRowShr + 2, 0xf, false>(x);
+  x += dpp<kRowShr + 4, 0xf, false>(x);
+  x += dpp<kRowShr + 8, 0xf, false>(x);
+  x += dpp<kRowBcast15, 0xa, false>(x);
+  x += dpp<kRowBcast31, 0xc, false>(x);
+  return x;
 }
-__device__ __forceinline__ int wave_sum(int v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+
+__device__ __forceinline__ int lane63(int v) { return __builtin_amdgcn_readlane(v, 63); }
+
+__device__ __forceinline__ int wave_sum(int v) { return lane63(wave_incl_scan(v)); }
+
+template <bool MAX>
+__device__ __forceinline__ int wave_ext(int v) {
+  auto f = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+  v = f(v, dpp<kRowShr + 1, 0xf, true>(v));
+  v = f(v, dpp<kRowShr + 2, 0xf, true>(v));
+  v = f(v, dpp<kRowShr + 4, 0xf, true>(v));
+  v = f(v, dpp<kRowShr + 8, 0xf, true>(v));
+  v = f(v, dpp<kRowBcast15, 0xa, true>(v));
+  v = f(v, dpp<kRowBcast31, 0xc, true>(v));
+  return lane63(v);
 }
+__device__ __forceinline__ int wave_max(int v) { return wave_ext<true>(v); }
+__device__ __forceinline__ int wave_min(int v) { return wave_ext<false>(v); }
 
 // source operand of a leaf for instruction encoding
 __device__ __forceinline__ void leaf_src(int r, float value, int& src, float& pay) {
@@ -121,15 +147,6 @@ __host__ __device__ constexpr size_t plan_lds_bytes(int Lmax) {
 // and of the ancestor sums D: code start (0..11), spill base (12..15), record shift (16..)
 constexpr int kStartBits = 12;
 
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(x, off, kWave);
-    if (lane >= off) x += y;
-  }
-  return x;
-}
-
 // NCH = node chunks of 64 held in registers while the row is decoded (Lmax <= 64 NCH)
 template <int NCH>
 __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
@@ -165,7 +182,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       sv[ch] = srow[i];
     }
   }
-  const float s0 = a.check_tail ? __shfl(sv[0], 0, kWave) : srow[0];
+  const float s0 = a.check_tail ? __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sv[0]))) : srow[0];
 
   int status = 0;
   int len = 0;
@@ -268,13 +285,13 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     const int nch = (len + kWave - 1) / kWave;
     for (int ch = nch - 1; ch >= 0; --ch) {
       const int i = ch * kWave + lane;
-      int x = (i < len) ? 1 - rec_arity(s_rec[i]) : 0;
-      for (int off = 1; off < kWave; off <<= 1) {
-        const int y = __shfl_down(x, off, kWave);
-        if (lane + off < kWave) x += y;
-      }
-      if (i < len) best = max(best, x + carry);
-      carry += __shfl(x, 0, kWave);
+      const int x = (i < len) ? 1 - rec_arity(s_rec[i]) : 0;
+      // suffix sum within the chunk: chunk total - inclusive prefix + own term
+      const int incl = wave_incl_scan(x);
+      const int tot = lane63(incl);
+      const int suf = tot - incl + x;
+      if (i < len) best = max(best, suf + carry);
+      carry += tot;
     }
     max_stack = wave_max(best);
 
@@ -301,9 +318,9 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
             x = cc | (1 << 16);
           }
         }
-        const int incl = wave_incl_scan(x, lane);
+        const int incl = wave_incl_scan(x);
         if (i < len) s_E[i + 1] = acc + incl;
-        acc += __shfl(incl, kWave - 1, kWave);
+        acc += lane63(incl);
       }
       if (lane == 0) s_E[0] = 0;
     }
@@ -353,7 +370,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       for (int ch = 0; ch < nch; ++ch) {
         const int i = ch * kWave + lane;
         const int x = i < len ? s_D[i] : 0;
-        const int incl = wave_incl_scan(x, lane);
+        const int incl = wave_incl_scan(x);
         if (i < len) {
           const int d = acc + incl;
           s_D[i] = d;
@@ -364,7 +381,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
               max_base = max(max_base, (d >> kStartBits) & 15);
           }
         }
-        acc += __shfl(incl, kWave - 1, kWave);
+        acc += lane63(incl);
       }
     }
     __syncthreads();
@@ -532,6 +549,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     info[kInfoProgLen] = prog_len;
     info[kInfoNeed] = need0;
     info[kInfoNInternal] = n_int;
+    info[kInfoHdr] = (int32_t)((uint32_t)t | (status != 0 ? kHdrInvalid : 0u) | (n_modi > 0 ? kHdrModi : 0u));
     a.acc[t] = 0.0;
     if (a.out_status) a.out_status[t] = status;
     if (a.out_info) {
@@ -592,7 +610,7 @@ __global__ __launch_bounds__(kOrderBlock) void order_kernel(OrderArgs a) {
     base[key] = cnt[key] > 0 ? off + atomicAdd(&a.cursor[key], cnt[key]) : 0;
   }
   __syncthreads();
-  if (k >= 0) a.order[base[k] + rank] = (int32_t)t;
+  if (k >= 0) a.order[base[k] + rank] = a.info[t * kInfoStride + kInfoHdr];
 }
 
 hipError_t launch_prep(int32_t* counters, int n, hipStream_t s) {

@@ -79,7 +79,11 @@ __host__ __device__ constexpr uint32_t mkword(int c, int aux = 0) {
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]
 constexpr int kInfoStatus = 0, kInfoLen = 1, kInfoMaxStack = 2, kInfoNConst = 3, kInfoNModi = 4,
-              kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoNInternal = 8, kInfoStride = 10;
+              kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoNInternal = 8, kInfoHdr = 9,
+              kInfoStride = 10;
+
+// tree header word (info[kInfoHdr]) and persistent order entries: tree index in the low 30 bits
+constexpr uint32_t kHdrInvalid = 1u << 31, kHdrModi = 1u << 30, kHdrTree = (1u << 30) - 1;
 
 // ---- adjoint records ----
 // One record (8 x uint32) per function node, in pre-order with the smaller

@@ -27,17 +27,17 @@ struct PlanArgs {
   int32_t* out_status;  // optional [P]
 };
 
-// persistent work queues: one counter per XCD-sized share of the grid, each
-// in its own cache line, so that the unit counters are not one hot line
-constexpr int kMaxQueues = 8;
-constexpr int kQueueStride = 32;
+// persistent work queues: one counter per point tile, each in its own
+// 64-byte line (waves bound to one tile share its counter)
+constexpr int kMaxTileQueues = 1024;  // counters for all tiles' sub-queues
+constexpr int kQueueStride = 16;
 
 struct OrderArgs {
   const int32_t* info;
   int64_t P;
   int32_t* hist;        // [16] valid trees per length bucket, zero on entry
   int32_t* cursor;      // [17], zero on entry (16 buckets + invalid trees)
-  int32_t* order;       // [P] tree indices, longest length bucket first
+  int32_t* order;       // [P] tree headers (index | kHdr* flags), longest length bucket first
 };
 
 struct EvalArgs {
@@ -60,9 +60,10 @@ struct EvalArgs {
   int32_t ntiles;       // point tiles of 64*K points
   int32_t ngroups;      // tile groups of block_waves tiles (tree-major / point-major)
   int32_t tpu;          // trees per unit
-  int64_t n_units;      // persistent: number of (tree chunk, tile) units
-  int32_t* queue;       // persistent: nq unit counters kQueueStride ints apart, zero on entry
-  int32_t nq;           // persistent: number of queues (workgroup b draws from queue b % nq)
+  int32_t* queue;       // persistent: ntiles chunk counters kQueueStride ints apart, zero on entry
+  int32_t wpt;          // persistent: waves bound to each tile
+  int32_t dynamic;      // persistent: chunks from the tile counters (else round-robin)
+  int32_t nsub;         // persistent dynamic: sub-queues (counters) per tile
 };
 
 struct AdjArgs {

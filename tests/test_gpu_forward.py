@@ -121,7 +121,9 @@ def test_invalid_trees_status_and_nan():
 
 MODES = [("tree", dict(mode=1)), ("tree-bw1", dict(mode=1, block_waves=1)), ("point", dict(mode=2)),
          ("point-tpu7", dict(mode=2, trees_per_unit=7)), ("persist", dict(mode=3)),
-         ("persist-tpu1", dict(mode=3, trees_per_unit=1))]
+         ("persist-tpu1", dict(mode=3, trees_per_unit=1)),
+         ("persist-tpu3-bw2", dict(mode=3, trees_per_unit=3, block_waves=2)),
+         ("persist-static-tpu2", dict(mode=3, trees_per_unit=2, flags=2))]
 
 
 @pytest.mark.parametrize("K", [16, 8, 4])
