@@ -92,17 +92,12 @@ __device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, 1>& s, 
   }
 }
 
-// value of a child for this lane's K points: variable, constant or recomputed subtree
+// value of a leaf child for this lane's K points
 template <int K, int VM>
-__device__ __forceinline__ void child_value(Regs<K, VM, 1>& s, float* spill, prog_ptr prog, int kind, int var,
-                                            uint32_t w1, uint32_t w2, float out[K]) {
-  if (kind == kKindFunc) {
-    run_program<K, VM, 1, true>(prog + w1, s, spill, (int)w2);
+__device__ __forceinline__ void leaf_value(const Regs<K, VM, 1>& s, int kind, int var, uint32_t bits, float out[K]) {
+  if (kind == kKindConst) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) out[j] = s.A[j];
-  } else if (kind == kKindConst) {
-#pragma unroll
-    for (int j = 0; j < K; ++j) out[j] = __uint_as_float(w2);
+    for (int j = 0; j < K; ++j) out[j] = __uint_as_float(bits);
   } else {
 #pragma unroll
     for (int v = 0; v < VM; ++v)
@@ -168,53 +163,122 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
     if (status != 0) continue;
     const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
     const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
+    const int plen = __builtin_amdgcn_readfirstlane(inf[kInfoProgLen]);
     const float gt = a.grad_mse ? a.grad_mse[t] : 1.0f;
     prog_ptr prog = (prog_ptr)(a.prog + t * a.pstride);
-
-    // ---- forward: output, fitness, output adjoint ----
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      s.A[j] = 0.0f;
-      s.O[0][j] = 0.0f;
-    }
-    run_program<K, VM, 1, false>(prog, s, spill);
-    float gbar[K];
-    double sse = 0.0;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const int64_t p = p0 + j * kWave;
-      const float out = nmodi ? s.O[0][j] : s.A[j];
-      gbar[j] = 0.0f;
-      if (p < a.D) {
-        const float e = out - a.Y[p];
-        sse += (double)(e * e);
-        gbar[j] = gt * 2.0f * e * a.inv_D;
-      }
-    }
-    sse = wave_sum_f64(sse);
-    if (lane == 0) unsafeAtomicAdd(&a.acc[t], sse);
-
-    // ---- reverse sweep over the adjoint records ----
-    if (nint == 0) {  // the tree is a single leaf
-      const uint2 ins = a.prog[t * a.pstride];
-      const int src = (int)(ins.x & 0xffffu) - kLD;
-      if (src >= kSrcX0)
-        leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
-      else
-        leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
-      continue;
-    }
     rec_ptr recs = (rec_ptr)(a.adj + t * (int64_t)a.Lmax * kAdjWords);
-    float cur[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+
+    float gbar[K], cur[K];
     int sp = 0;
-    for (int q = 0; q < nint; ++q) {
-      const uint32_t w0 = recs[kAdjWords * q], w1 = recs[kAdjWords * q + 1], w2 = recs[kAdjWords * q + 2];
-      const uint32_t w3 = recs[kAdjWords * q + 3], w4 = recs[kAdjWords * q + 4];
-      const int op = w0 & 15, ar = (w0 >> 4) & 3, modi = (w0 >> 6) & 1, c2first = (w0 >> 7) & 1;
+    // Step q = -1 is the forward pass (the whole program but its END); step
+    // q >= 0 is adjoint record q. Every interpreter run of the tree happens
+    // at the one call site below, so the kernel holds one copy of the
+    // interpreter's dispatch code.
+    for (int q = -1; q < nint; ++q) {
+      uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0;
+      int op = 0, ar = 0, k1 = kKindNone, k2 = kKindNone, v1 = 0, v2 = 0;
+      float va[K], vb[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) va[j] = vb[j] = 0.0f;
+      // interpreter runs of this step: start, length, destination (0: va, 1: vb, 2: forward)
+      uint32_t rs0 = 0, rl0 = 0, rs1 = 0, rl1 = 0;
+      int nrun = 0, d0 = 2, d1 = 1;
+      if (q < 0) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          s.A[j] = 0.0f;
+          s.O[0][j] = 0.0f;
+        }
+        nrun = 1;
+        rs0 = 0;
+        rl0 = (uint32_t)(plen - 1);
+        d0 = 2;
+      } else {
+        w0 = recs[kAdjWords * q];
+        w1 = recs[kAdjWords * q + 1];
+        w2 = recs[kAdjWords * q + 2];
+        w3 = recs[kAdjWords * q + 3];
+        w4 = recs[kAdjWords * q + 4];
+        op = w0 & 15;
+        ar = (w0 >> 4) & 3;
+        k1 = (w0 >> 10) & 3;
+        k2 = (w0 >> 12) & 3;
+        v1 = (w0 >> 14) & 15;
+        v2 = (w0 >> 18) & 15;
+        // children values (not needed for add / sub)
+        if (op != kOpAdd && op != kOpSub) {
+          if (k1 == kKindFunc) {
+            rs0 = w1;
+            rl0 = w2;
+            d0 = 0;
+            nrun = 1;
+          } else {
+            leaf_value<K, VM>(s, k1, v1, w2, va);
+          }
+          if (ar == 2) {
+            if (k2 == kKindFunc) {
+              if (nrun == 0) {
+                rs0 = w3;
+                rl0 = w4;
+                d0 = 1;
+              } else {
+                rs1 = w3;
+                rl1 = w4;
+                d1 = 1;
+              }
+              ++nrun;
+            } else {
+              leaf_value<K, VM>(s, k2, v2, w4, vb);
+            }
+          }
+        }
+      }
+#pragma nounroll
+      for (int r = 0; r < nrun; ++r) {
+        const uint32_t rs = r == 0 ? rs0 : rs1, rl = r == 0 ? rl0 : rl1;
+        const int dst = r == 0 ? d0 : d1;
+        run_program<K, VM, 1, true>(prog + rs, s, spill, (int)rl);
+        if (dst == 0) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) va[j] = s.A[j];
+        } else if (dst == 1) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) vb[j] = s.A[j];
+        }
+      }
+
+      if (q < 0) {
+        // ---- forward: output, fitness, output adjoint ----
+        double sse = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int64_t p = p0 + j * kWave;
+          const float out = nmodi ? s.O[0][j] : s.A[j];
+          gbar[j] = 0.0f;
+          if (p < a.D) {
+            const float e = out - a.Y[p];
+            sse += (double)(e * e);
+            gbar[j] = gt * 2.0f * e * a.inv_D;
+          }
+        }
+        sse = wave_sum_f64(sse);
+        if (lane == 0) unsafeAtomicAdd(&a.acc[t], sse);
+        if (nint == 0) {  // the tree is a single leaf
+          const uint2 ins = a.prog[t * a.pstride];
+          const int src = word_case(ins.x) - kLD;
+          if (src >= kSrcX0)
+            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
+          else
+            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+        continue;
+      }
+
+      // ---- adjoint record q ----
+      const int modi = (w0 >> 6) & 1, c2first = (w0 >> 7) & 1;
       const int pop = (w0 >> 8) & 1, push = (w0 >> 9) & 1;
-      const int k1 = (w0 >> 10) & 3, k2 = (w0 >> 12) & 3, v1 = (w0 >> 14) & 15, v2 = (w0 >> 18) & 15;
       float adj[K];
       if (pop) {
         sp = sp > 0 ? sp - 1 : 0;
@@ -223,14 +287,6 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
       } else {
 #pragma unroll
         for (int j = 0; j < K; ++j) adj[j] = cur[j];
-      }
-      // children values (not needed for add / sub)
-      float va[K], vb[K];
-#pragma unroll
-      for (int j = 0; j < K; ++j) va[j] = vb[j] = 0.0f;
-      if (op != kOpAdd && op != kOpSub) {
-        child_value<K, VM>(s, spill, prog, k1, v1, w1, w2, va);
-        if (ar == 2) child_value<K, VM>(s, spill, prog, k2, v2, w3, w4, vb);
       }
       float a1[K], a2[K];
 #pragma unroll

@@ -15,8 +15,6 @@ constexpr int kWave = 64;
 template <int K>
 constexpr int kLdsFloatsPerWave = (kMaxSlots - kRegSlots) * K * kWave;
 
-// interpreter actions after the dispatch switch
-constexpr int kActModi = 8, kActUn = 16, kActStop = 32;
 
 template <int K, int VM, int NO>
 struct Regs {
@@ -104,9 +102,36 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     const unsigned long long nxt = prog[0];
     const uint32_t w = (uint32_t)ins;
     const float cv = __uint_as_float((uint32_t)(ins >> 32));
-    const int c = (int)(w & 0xffffu);
-    const int aux = (int)(w >> 16);
-    int act = 0;
+    const int c = word_case(w);
+    const int aux = (int)(w >> kAuxShift);
+    int act = (int)((w >> kActShift) & 63u);
+
+    // spill A first (the word is the first load of a second-evaluated subtree)
+    if (w & kSpillFlag) {
+      switch ((w >> kSpillShift) & 7u) {
+        case 0:
+#pragma unroll
+          for (int j = 0; j < K; ++j) s.R[0][j] = s.A[j];
+          break;
+        case 1:
+#pragma unroll
+          for (int j = 0; j < K; ++j) s.R[1][j] = s.A[j];
+          break;
+        case 2:
+#pragma unroll
+          for (int j = 0; j < K; ++j) s.R[2][j] = s.A[j];
+          break;
+        case 3:
+#pragma unroll
+          for (int j = 0; j < K; ++j) s.R[3][j] = s.A[j];
+          break;
+        default: {
+          float* dst = spill + ((int)((w >> kSpillShift) & 7u) - kRegSlots) * (K * kWave);
+#pragma unroll
+          for (int j = 0; j < K; ++j) dst[j * kWave] = s.A[j];
+        } break;
+      }
+    }
 
 #define TGP_SRC_CASE(BASE, S, STMT)                                   \
   case (BASE) + (S): {                                                \
@@ -127,13 +152,7 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
   TGP_SRC_CASE(BASE, 18, STMT) TGP_SRC_CASE(BASE, 19, STMT) TGP_SRC_CASE(BASE, 20, STMT)    \
   TGP_SRC_CASE(BASE, 21, STMT)
 
-#define TGP_BT_CASE(B)                                                                      \
-  case kBT + 2 * (B):                                                                       \
-    _Pragma("unroll") for (int j = 0; j < K; ++j) s.A[j] = bin_op<(B)>(s.A[j], s.T[j]);     \
-    break;                                                                                  \
-  case kBT + 2 * (B) + 1:                                                                   \
-    _Pragma("unroll") for (int j = 0; j < K; ++j) s.A[j] = bin_op<(B)>(s.T[j], s.A[j]);     \
-    break;                                                                                  \
+#define TGP_MB_CASE(B)                                                                      \
   case kMB + 2 * (B):                                                                       \
     _Pragma("unroll") for (int j = 0; j < K; ++j) {                                         \
       s.r[j] = bin_op<(B)>(s.A[j], s.T[j]);                                                 \
@@ -144,18 +163,11 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     _Pragma("unroll") for (int j = 0; j < K; ++j) s.r[j] = bin_op<(B)>(s.T[j], s.A[j]);     \
     break;
 
-// Unary (transcendental) cases only record which function to apply: the
-// library implementations branch per lane, and keeping those divergent
-// branches out of the dispatch switch keeps the switch a purely scalar
-// branch tree (no per-lane flow merges that copy the register state).
-#define TGP_UN_CASE(U)          \
-  case kUN + (U):               \
-    act = kActUn | (U);         \
-    break;                      \
-  case kMU + (U):               \
-    act = kActUn | kActModi | (U); \
-    break;
-
+// Unary (transcendental) functions are applied after the switch, from the
+// word's action bits: the library implementations branch per lane, and
+// keeping those divergent branches out of the dispatch switch keeps the
+// switch a purely scalar branch tree (no per-lane flow merges that copy the
+// register state).
     switch (c) {
       TGP_SRC_CASES(kLD, s.A[j] = v)
       TGP_SRC_CASES(kTLD, s.T[j] = v)
@@ -167,45 +179,16 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
       TGP_SRC_CASES(kSUBR, s.A[j] = v - s.A[j])
       TGP_SRC_CASES(kDIVA, s.A[j] = bin_op<3>(s.A[j], v))
       TGP_SRC_CASES(kDIVR, s.A[j] = bin_op<3>(v, s.A[j]))
-      case kSPL + 0:
-#pragma unroll
-        for (int j = 0; j < K; ++j) s.R[0][j] = s.A[j];
-        break;
-      case kSPL + 1:
-#pragma unroll
-        for (int j = 0; j < K; ++j) s.R[1][j] = s.A[j];
-        break;
-      case kSPL + 2:
-#pragma unroll
-        for (int j = 0; j < K; ++j) s.R[2][j] = s.A[j];
-        break;
-      case kSPL + 3:
-#pragma unroll
-        for (int j = 0; j < K; ++j) s.R[3][j] = s.A[j];
-        break;
-      case kSPLM: {
-        float* dst = spill + ((aux & (kMaxSlots - 1)) - kRegSlots) * (K * kWave);
-#pragma unroll
-        for (int j = 0; j < K; ++j) dst[j * kWave] = s.A[j];
-      } break;
-      case kTA:
-#pragma unroll
-        for (int j = 0; j < K; ++j) s.T[j] = s.A[j];
-        break;
-      TGP_BT_CASE(0)
-      TGP_BT_CASE(1)
-      TGP_BT_CASE(2)
-      TGP_BT_CASE(3)
-      TGP_BT_CASE(4)
-      TGP_BT_CASE(5)
-      TGP_UN_CASE(0)
-      TGP_UN_CASE(1)
-      TGP_UN_CASE(2)
-      TGP_UN_CASE(3)
-      TGP_UN_CASE(4)
-      TGP_UN_CASE(5)
+      TGP_MB_CASE(0)
+      TGP_MB_CASE(1)
+      TGP_MB_CASE(2)
+      TGP_MB_CASE(3)
+      TGP_MB_CASE(4)
+      TGP_MB_CASE(5)
       case kACC:
         add_out<K, VM, NO>(s, aux);
+        break;
+      case kNOP:
         break;
       default:  // kEND (or any word that is not an instruction)
         act = kActStop;
@@ -213,8 +196,7 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     }
 #undef TGP_SRC_CASE
 #undef TGP_SRC_CASES
-#undef TGP_BT_CASE
-#undef TGP_UN_CASE
+#undef TGP_MB_CASE
     if (BOUNDED) {
       if (--left == 0) act |= kActStop;
     }

@@ -51,12 +51,18 @@ __device__ __forceinline__ bool fused_op(int op) {
   return op == kOpAdd || op == kOpSub || op == kOpMul || op == kOpDiv || op == kOpMax || op == kOpMin;
 }
 
-// number of instructions a function node emits for its own operation
+// number of instructions a function node emits for its own operation (a
+// unary node over a leaf emits its load with the function in the action
+// bits, which is the same count)
 __device__ __forceinline__ int own_code(int r) {
   const int a = rec_arity(r);
-  if (rec_modi(r) >= 0) return a == 2 ? 3 : 2;  // [TLD] MB/MU ACC
-  if (a == 2) return fused_op(rec_op(r)) ? 1 : 2;
-  return 1;
+  if (rec_modi(r) >= 0) return a == 2 ? 3 : 2;  // TLD MB ACC | (LD or NOP) + action, ACC
+  return 1;                                     // fused binary op | (LD or NOP) + action
+}
+
+// action bits of a unary node: its function, for the Modi register if Modi
+__device__ __forceinline__ int unary_act(int op, int mo) {
+  return kActUn | un_index(op) | (mo >= 0 ? kActModi : 0);
 }
 
 // Wave-wide integer reductions and scans with DPP row shifts and row
@@ -109,6 +115,13 @@ __device__ __forceinline__ void leaf_src(int r, float value, int& src, float& pa
   }
 }
 
+// a load of leaf source `src`, with action bits, spilling A first when the
+// spill map says so (pre = slot + 1)
+__device__ __forceinline__ uint32_t load_word(int src, int act, int pre) {
+  const uint32_t w = mkword(kLD + src, 0, act);
+  return pre ? with_spill(w, pre - 1) : w;
+}
+
 __device__ __forceinline__ void put(uint2* __restrict__ prog, int64_t cap, int pos, uint32_t w, float pay) {
   if (pos >= 0 && pos < cap) prog[pos] = make_uint2(w, __float_as_uint(pay));
 }
@@ -140,7 +153,8 @@ __device__ __forceinline__ int fused_case(int op, bool a_first, int src) {
 // (int, Lmax + 1 entries each, rounded up) and subtree size (short).
 __host__ __device__ constexpr int plan_lpad(int Lmax) { return (Lmax + kWave) / kWave * kWave; }
 __host__ __device__ constexpr size_t plan_lds_bytes(int Lmax) {
-  return (size_t)plan_lpad(Lmax) * (3 * sizeof(int) + sizeof(short));
+  // + one byte per program word: spill slot + 1 to set on the load at that word, or 0
+  return (size_t)plan_lpad(Lmax) * (3 * sizeof(int) + sizeof(short)) + (size_t)(prog_stride(Lmax) + 3) / 4 * 4;
 }
 
 // packed fields of the prefix sums E: code size (bits 0..15), function nodes (16..31)
@@ -156,6 +170,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   int* s_E = s_rec + Lp;  // s_E[i] = sum over nodes < i (code size | function count << 16)
   int* s_D = s_E + Lp;    // difference array, then ancestor sums (start | base << 12 | shift << 16)
   short* s_sz = (short*)(s_D + Lp);
+  unsigned char* s_pre = (unsigned char*)(s_sz + Lp);  // per program word: spill slot + 1, or 0
 
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
@@ -308,13 +323,11 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
             const int c1 = i + 1;
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
             int cc = own_code(r);
-            if (rec_arity(r) == 1) {
-              cc += l1 ? 1 : 0;  // LD of the leaf operand
-            } else {
+            if (rec_arity(r) == 2) {
               const bool l2 = rec_kind(s_rec[c1 + s_sz[c1]]) != kTypeFunc;
-              cc += (l1 && l2) ? 1 : 0;    // LD of the first leaf
-              cc += (!l1 && !l2) ? 1 : 0;  // spill of the first-evaluated child
+              cc += (l1 && l2) ? 1 : 0;  // LD of the first leaf
             }
+            (void)l1;
             x = cc | (1 << 16);
           }
         }
@@ -352,7 +365,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int F = f1 ? c1 : c2, zF = f1 ? z1 : z2;
       const int S = f1 ? c2 : c1, zS = f1 ? z2 : z1;
       const int csF = (s_E[F + zF] - s_E[F]) & 0xffff;
-      const int v = (csF + 1) + (1 << kStartBits);
+      const int v = csF + (1 << kStartBits);
       atomicAdd(&s_D[S], v);
       atomicAdd(&s_D[S + zS], -v);
       if (a.adj && z2 < z1) {
@@ -390,12 +403,30 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     prog_len = rec_kind(root) == kTypeFunc ? (s_E[len] & 0xffff) + 1 : 2;
     n_int = s_E[len] >> 16;
 
+    // spill map: the first word of every second-evaluated subtree (always a
+    // load) first stores A, the first-evaluated sibling's value, to the
+    // parent's spill slot
+    for (int k = lane; k <= prog_len; k += kWave) s_pre[k] = 0;
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int i = ch * kWave + lane;
+      if (i >= len) continue;
+      const int r = s_rec[i];
+      if (rec_kind(r) != kTypeFunc || rec_arity(r) != 2) continue;
+      const int c1 = i + 1, z1 = s_sz[c1], c2 = c1 + z1;
+      if (rec_kind(s_rec[c1]) != kTypeFunc || rec_kind(s_rec[c2]) != kTypeFunc) continue;
+      const int S = z1 >= s_sz[c2] ? c2 : c1;
+      const int stS = s_D[S] & ((1 << kStartBits) - 1);
+      if (stS <= prog_len) s_pre[stS] = (unsigned char)(((s_D[i] >> kStartBits) & 15) + 1);
+    }
+    __syncthreads();
+
     // ---- pass 6: emission ----
     if (rec_kind(root) != kTypeFunc) {
       if (lane == 0) {
         int src; float pay;
         leaf_src(root, vrow[0], src, pay);
-        put(prog, a.pstride, 0, mkword(kLD + src), pay);
+        put(prog, a.pstride, 0, mkword(kLD + src), pay);  // a leaf root has no spill
       }
     }
     for (int ch = 0; ch < nch; ++ch) {
@@ -414,17 +445,16 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int r1 = s_rec[c1];
       const bool l1 = rec_kind(r1) != kTypeFunc;
       if (rec_arity(r) == 1) {
+        // over a leaf: its load carries the function; otherwise a NOP does
+        uint32_t wd = mkword(kNOP, 0, unary_act(op, mo));
+        float pay = 0.0f;
         if (l1) {
-          int src; float pay;
+          int src;
           leaf_src(r1, vrow[c1], src, pay);
-          put(prog, a.pstride, st, mkword(kLD + src), pay);
+          wd = load_word(src, unary_act(op, mo), s_pre[pos]);
         }
-        if (mo < 0) {
-          put(prog, a.pstride, pos, mkword(kUN + un_index(op)), 0.0f);
-        } else {
-          put(prog, a.pstride, pos, mkword(kMU + un_index(op)), 0.0f);
-          put(prog, a.pstride, pos + 1, mkword(kACC, mo), 0.0f);
-        }
+        put(prog, a.pstride, pos, wd, pay);
+        if (mo >= 0) put(prog, a.pstride, pos + 1, mkword(kACC, mo), 0.0f);
         continue;
       }
       const int z1 = s_sz[c1];
@@ -437,7 +467,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (l1 && l2) {
         int s1; float p1;
         leaf_src(r1, vrow[c1], s1, p1);
-        put(prog, a.pstride, st, mkword(kLD + s1), p1);
+        put(prog, a.pstride, st, load_word(s1, 0, s_pre[st]), p1);
         leaf_src(r2, vrow[c2], src, pay);
         a_first = true;
       } else if (l1) {
@@ -448,12 +478,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         a_first = true;
       } else {
         const bool f1 = z1 >= s_sz[c2];
-        const int F = f1 ? c1 : c2;
-        const int csF = (s_E[F + s_sz[F]] - s_E[F]) & 0xffff;
         int saux;
-        if (bs < kRegSlots) put(prog, a.pstride, st + csF, mkword(kSPL + bs), 0.0f);
-        else put(prog, a.pstride, st + csF, mkword(kSPLM, bs), 0.0f);
-        src = src_slot(bs, saux);
+        src = src_slot(bs, saux);  // the spill happens on the second subtree's first load
         aux = saux;
         a_first = !f1;  // the first-evaluated child is in the slot
       }
@@ -461,11 +487,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
         put(prog, a.pstride, pos + 1, mkword(kMB + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
         put(prog, a.pstride, pos + 2, mkword(kACC, mo), 0.0f);
-      } else if (fused_op(op)) {
-        put(prog, a.pstride, pos, mkword(fused_case(op, a_first, src), aux), pay);
       } else {
-        put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
-        put(prog, a.pstride, pos + 1, mkword(kBT + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
+        put(prog, a.pstride, pos, mkword(fused_case(op, a_first, src), aux), pay);
       }
     }
     if (lane == 0) {

@@ -50,7 +50,17 @@ constexpr int kMaxSlots = 8;       // spill slots in total (need <= 8 for len <=
 // cannot reach form one contiguous range per group)
 constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 
-// ---- cases ----
+// ---- instruction word ----
+// A program is a sequence of 8-byte words: 32 bits of code, then a float
+// payload (the constant of a constant source). Code bits:
+//    0..8   case (below): the data movement or arithmetic on A
+//    9..11  spill slot, 12 spill flag: before the case, store A to that
+//           slot (the value of a first-evaluated subtree, saved while its
+//           sibling is computed; always carried by the sibling's first load)
+//   16..21  action after the case: kActUn | unary index applies a unary
+//           function to A (to the Modi register r instead with kActModi);
+//           kActStop ends the program
+//   22..31  aux: LDS slot of a kSrcRM source, output index of kACC
 constexpr int kLD = 0;                    // A = src
 constexpr int kTLD = kLD + kNumSrc;       // T = src
 constexpr int kADD = kTLD + kNumSrc;      // A = A + src
@@ -61,20 +71,24 @@ constexpr int kSUBA = kMIN + kNumSrc;     // A = A - src
 constexpr int kSUBR = kSUBA + kNumSrc;    // A = src - A
 constexpr int kDIVA = kSUBR + kNumSrc;    // A = A / src (protected)
 constexpr int kDIVR = kDIVA + kNumSrc;    // A = src / A (protected)
-constexpr int kSPL = kDIVR + kNumSrc;     // R[k] = A, k < 4
-constexpr int kSPLM = kSPL + kRegSlots;   // LDS slot aux = A
-constexpr int kTA = kSPLM + 1;            // T = A
-constexpr int kBT = kTA + 1;              // A = op(A,T) (ord 0) or op(T,A) (ord 1): kBT + 2*bin_index + ord
-constexpr int kUN = kBT + 12;             // A = f(A): kUN + un_index
-constexpr int kMB = kUN + 6;              // r = op(A,T)|op(T,A); A = second operand's value
-constexpr int kMU = kMB + 12;             // r = f(A)
-constexpr int kACC = kMU + 6;             // O[aux] += r
-constexpr int kEND = kACC + 1;
+constexpr int kMB = kDIVR + kNumSrc;      // Modi binary: r = op(A,T) (ord 0) or op(T,A) (ord 1),
+                                          // A = the second operand's value: kMB + 2*bin_index + ord
+constexpr int kACC = kMB + 12;            // O[aux] += r
+constexpr int kNOP = kACC + 1;            // nothing (the action bits do the work)
+constexpr int kEND = kNOP + 1;            // stop
 constexpr int kNumCases = kEND + 1;
 
-__host__ __device__ constexpr uint32_t mkword(int c, int aux = 0) {
-  return (uint32_t)c | ((uint32_t)aux << 16);
+constexpr int kCaseBits = 9, kSpillShift = 9, kSpillFlag = 1 << 12, kActShift = 16, kAuxShift = 22;
+// actions (bits 16..21 of a word)
+constexpr int kActModi = 8, kActUn = 16, kActStop = 32;
+
+__host__ __device__ constexpr uint32_t mkword(int c, int aux = 0, int act = 0) {
+  return (uint32_t)c | ((uint32_t)act << kActShift) | ((uint32_t)aux << kAuxShift);
 }
+__host__ __device__ constexpr uint32_t with_spill(uint32_t w, int slot) {
+  return w | (uint32_t)kSpillFlag | ((uint32_t)slot << kSpillShift);
+}
+__host__ __device__ constexpr int word_case(uint32_t w) { return (int)(w & ((1u << kCaseBits) - 1)); }
 
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]
