@@ -103,10 +103,11 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     const uint32_t w = (uint32_t)ins;
     const float cv = __uint_as_float((uint32_t)(ins >> 32));
     const int c = word_case(w);
-    const int aux = (int)(w >> kAuxShift);
+    const int aux = (int)((w >> kAuxShift) & kAuxMask);
     int act = (int)((w >> kActShift) & 63u);
 
-    // spill A first (the word is the first load of a second-evaluated subtree)
+    if (w & (kSpillFlag | kPreLoadFlag)) {
+    // spill A first (the word starts a second-evaluated subtree)
     if (w & kSpillFlag) {
       switch ((w >> kSpillShift) & 7u) {
         case 0:
@@ -131,6 +132,17 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
           for (int j = 0; j < K; ++j) dst[j * kWave] = s.A[j];
         } break;
       }
+    }
+    // then load a variable (the first operand of a binary node over two leaves)
+    if (w & kPreLoadFlag) {
+      const int var = (int)((w >> kPreLoadShift) & 15u);
+#pragma unroll
+      for (int v = 0; v < VM; ++v)
+        if (v == var) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) s.A[j] = s.X[v][j];
+        }
+    }
     }
 
 #define TGP_SRC_CASE(BASE, S, STMT)                                   \

@@ -115,6 +115,12 @@ __device__ __forceinline__ void leaf_src(int r, float value, int& src, float& pa
   }
 }
 
+// a binary non-Modi node over two leaves, one of them a variable, is one
+// word: the variable is pre-loaded into A and the case takes the other leaf
+__device__ __forceinline__ bool preload_fusable(int r, int r1, int r2) {
+  return rec_modi(r) < 0 && (rec_kind(r1) == kTypeVar || rec_kind(r2) == kTypeVar);
+}
+
 // a load of leaf source `src`, with action bits, spilling A first when the
 // spill map says so (pre = slot + 1)
 __device__ __forceinline__ uint32_t load_word(int src, int act, int pre) {
@@ -324,10 +330,11 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
             int cc = own_code(r);
             if (rec_arity(r) == 2) {
-              const bool l2 = rec_kind(s_rec[c1 + s_sz[c1]]) != kTypeFunc;
-              cc += (l1 && l2) ? 1 : 0;  // LD of the first leaf
+              const int r2 = s_rec[c1 + s_sz[c1]];
+              const bool l2 = rec_kind(r2) != kTypeFunc;
+              // LD of the first leaf, unless a variable operand rides on the op word
+              if (l1 && l2 && !preload_fusable(r, s_rec[c1], r2)) cc += 1;
             }
-            (void)l1;
             x = cc | (1 << 16);
           }
         }
@@ -464,7 +471,17 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       int src, aux = 0;
       float pay = 0.0f;
       bool a_first;  // A holds the first operand and src the second
-      if (l1 && l2) {
+      if (l1 && l2 && preload_fusable(r, r1, r2)) {
+        // one word: pre-load the variable operand, the case takes the other leaf
+        const bool v1 = rec_kind(r1) == kTypeVar;
+        const int pv = v1 ? rec_var(r1) : rec_var(r2);
+        leaf_src(v1 ? r2 : r1, vrow[v1 ? c2 : c1], src, pay);
+        a_first = v1;
+        uint32_t wd = with_preload(mkword(fused_case(op, a_first, src), aux), pv);
+        if (s_pre[pos]) wd = with_spill(wd, s_pre[pos] - 1);
+        put(prog, a.pstride, pos, wd, pay);
+        continue;
+      } else if (l1 && l2) {
         int s1; float p1;
         leaf_src(r1, vrow[c1], s1, p1);
         put(prog, a.pstride, st, load_word(s1, 0, s_pre[st]), p1);

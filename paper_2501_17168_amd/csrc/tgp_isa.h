@@ -56,11 +56,14 @@ constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 //    0..8   case (below): the data movement or arithmetic on A
 //    9..11  spill slot, 12 spill flag: before the case, store A to that
 //           slot (the value of a first-evaluated subtree, saved while its
-//           sibling is computed; always carried by the sibling's first load)
+//           sibling is computed; always carried by the sibling's first word)
 //   16..21  action after the case: kActUn | unary index applies a unary
 //           function to A (to the Modi register r instead with kActModi);
 //           kActStop ends the program
-//   22..31  aux: LDS slot of a kSrcRM source, output index of kACC
+//   22..24  aux: LDS slot of a kSrcRM source, output index of kACC
+//   25      pre-load flag, 26..29 variable: after the spill and before the
+//           case, A = x[variable] (a binary node over two leaves is then
+//           one word)
 constexpr int kLD = 0;                    // A = src
 constexpr int kTLD = kLD + kNumSrc;       // T = src
 constexpr int kADD = kTLD + kNumSrc;      // A = A + src
@@ -79,6 +82,7 @@ constexpr int kEND = kNOP + 1;            // stop
 constexpr int kNumCases = kEND + 1;
 
 constexpr int kCaseBits = 9, kSpillShift = 9, kSpillFlag = 1 << 12, kActShift = 16, kAuxShift = 22;
+constexpr int kAuxMask = 7, kPreLoadFlag = 1 << 25, kPreLoadShift = 26;
 // actions (bits 16..21 of a word)
 constexpr int kActModi = 8, kActUn = 16, kActStop = 32;
 
@@ -89,6 +93,9 @@ __host__ __device__ constexpr uint32_t with_spill(uint32_t w, int slot) {
   return w | (uint32_t)kSpillFlag | ((uint32_t)slot << kSpillShift);
 }
 __host__ __device__ constexpr int word_case(uint32_t w) { return (int)(w & ((1u << kCaseBits) - 1)); }
+__host__ __device__ constexpr uint32_t with_preload(uint32_t w, int var) {
+  return w | (uint32_t)kPreLoadFlag | ((uint32_t)var << kPreLoadShift);
+}
 
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]
