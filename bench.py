@@ -180,13 +180,13 @@ def cpu_baseline(w, seconds, max_workers=16):
         k1 += 1
     el1 = time.perf_counter() - t0
     rate1 = len1 * w.D / el1
-    # all cores: the rest of the random order, up to about `seconds` of CPU work in total
+    # all cores: the random order from its start, up to about `seconds` of one-core work (the
+    # whole workload when it is smaller)
     workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
-    rest = order[k1:]
-    budget = seconds * rate1 / w.D            # node-evals' worth of lengths one core does in `seconds`
-    cum = np.cumsum(lengths[rest])
-    n = int(np.searchsorted(cum, budget)) + 1 if len(rest) else 0
-    sample = rest[:n]
+    budget = seconds * rate1 / w.D            # lengths' worth of trees one core does in `seconds`
+    cum = np.cumsum(lengths[order])
+    n = min(w.P, int(np.searchsorted(cum, budget)) + 1)
+    sample = order[:n]
     res = {"value": rate1, "unit": "GPops/s", "cores": 1, "kind": "oracle",
            "sample": f"{k1} of {w.P} trees (random order) x all {w.D} points, float64 numpy, {el1:.1f} s on one core"}
     if workers > 1 and len(sample) >= workers:
