@@ -87,7 +87,7 @@ __device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, 1>& s, 
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const int64_t p = p0 + j * kWave;
-      s.X[v][j] = (v < a.V && p < a.D) ? a.X[(int64_t)v * a.ldx + p] : 0.0f;
+      s.X[v][j] = __builtin_canonicalizef((v < a.V && p < a.D) ? a.X[(int64_t)v * a.ldx + p] : 0.0f);
     }
   }
 }

@@ -68,7 +68,8 @@ __device__ __forceinline__ void load_tile(const EvalArgs& a, Regs<K, VM, NO>& s,
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const int64_t p = p0 + j * kWave;
-      s.X[v][j] = (v < a.V && p < a.D) ? xr[p] : 0.0f;
+      // canonical (a signaling NaN becomes quiet), as the interpreter's max/min assume
+      s.X[v][j] = __builtin_canonicalizef((v < a.V && p < a.D) ? xr[p] : 0.0f);
     }
   }
 #pragma unroll

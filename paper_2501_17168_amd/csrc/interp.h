@@ -26,14 +26,31 @@ struct Regs {
   float O[NO][K];
 };
 
+// max / min of canonical values. Every value the interpreter holds is the
+// result of an IEEE operation, a finite constant or a canonicalized X load,
+// so no operand is a signaling NaN; the hardware max/min then already has
+// fmax/fmin semantics (a quiet NaN operand is ignored) and the compiler's
+// per-operand canonicalization (two extra instructions per point) is not
+// needed.
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float vmin(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 template <int B>
 __device__ __forceinline__ float bin_op(float a, float b) {
   if constexpr (B == 0) return a + b;
   else if constexpr (B == 1) return a - b;
   else if constexpr (B == 2) return a * b;
   else if constexpr (B == 3) return fabsf(b) < kDivTau ? 1.0f : a / b;
-  else if constexpr (B == 4) return fmaxf(a, b);
-  else return fminf(a, b);
+  else if constexpr (B == 4) return vmax(a, b);
+  else return vmin(a, b);
 }
 
 template <int U>
@@ -185,8 +202,8 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
       TGP_SRC_CASES(kTLD, s.T[j] = v)
       TGP_SRC_CASES(kADD, s.A[j] = s.A[j] + v)
       TGP_SRC_CASES(kMUL, s.A[j] = s.A[j] * v)
-      TGP_SRC_CASES(kMAX, s.A[j] = fmaxf(s.A[j], v))
-      TGP_SRC_CASES(kMIN, s.A[j] = fminf(s.A[j], v))
+      TGP_SRC_CASES(kMAX, s.A[j] = vmax(s.A[j], v))
+      TGP_SRC_CASES(kMIN, s.A[j] = vmin(s.A[j], v))
       TGP_SRC_CASES(kSUBA, s.A[j] = s.A[j] - v)
       TGP_SRC_CASES(kSUBR, s.A[j] = v - s.A[j])
       TGP_SRC_CASES(kDIVA, s.A[j] = bin_op<3>(s.A[j], v))
