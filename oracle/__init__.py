@@ -16,3 +16,7 @@ from .tgp_oracle import (  # noqa: F401
     mse_tree_shadow32, predict, grad, grad_tree, fd_grad_const, fd_grad_x, adam_reference,
     apply_op, op_partials, length_bucket,
 )
+from .exchange_oracle import (  # noqa: F401
+    subtree_exchange, exchange_tree, ancestors, pick_node,
+    X_OK, X_TOO_LONG, X_BAD_OLD, X_BAD_DONOR, OLD_UNIFORM, NEW_UNIFORM,
+)
