@@ -166,6 +166,65 @@ tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
                         int32_t want_grad, tgp_cfg* out, void* ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* ---- subtree exchange (§III-B) ----
+ * exchange(T_old, k, T_new) replaces the subtree rooted at node k of T_old
+ * by T_new: with s = k and e = s + size_old[k], each row of the result is
+ * old[0, s), then T_new's row, then old[e, len_old); in the size row every
+ * ancestor of k first gains dn = size_new[root] - size_old[k]. When
+ * len_old + dn exceeds the length limit the exchange is refused and T_old
+ * is returned. One-point crossover inserts a subtree of another parent,
+ * subtree mutation a freshly generated tree, hoist mutation a subtree of
+ * T_old itself.
+ *
+ * Batch form: output tree b is exchange(old tree old_row[b], node k_b,
+ * subtree of donor tree new_row[b] rooted at node j_b). Node arguments are
+ * int32 indices, or, for a side whose TGP_XCHG_*_UNIFORM flag is set,
+ * float32 u in [0, 1) mapped to node floor(u * len) (product rounded to
+ * float32, clamped to len - 1; len = size[0] of that tree), so a random node
+ * of each tree is drawn on the device from caller-supplied uniforms.
+ *
+ * Per-output status (first failing check wins), and the row written:
+ *   TGP_XCHG_BAD_OLD   old_row[b] outside [0, old->P): all-NaN row;
+ *                      size_old[0] not an integer in [1, old->Lmax]: the
+ *                      old row copied verbatim;
+ *                      k outside [0, len_old) (or u not in [0, 1)), or
+ *                      size_old[k] not an integer in [1, len_old - k]: T_old;
+ *   TGP_XCHG_BAD_DONOR new_row[b] outside [0, donor->P); with the uniform
+ *                      flag, size_new[0] not an integer in [1, donor->Lmax]
+ *                      or u not in [0, 1); j outside [0, donor->Lmax), or
+ *                      size_new[j] not an integer in [1, donor->Lmax - j]:
+ *                      T_old;
+ *   TGP_XCHG_TOO_LONG  len_old + dn > max_len: T_old;
+ *   TGP_XCHG_OK        the exchanged tree.
+ * "T_old" is the old row's first len_old entries followed by NaN (for a
+ * valid tree, the row itself). The exchanged tree is what the definition
+ * gives for valid old and donor trees (tgp_plan status 0); for others only
+ * the checks above are made. */
+enum { TGP_XCHG_OK = 0, TGP_XCHG_TOO_LONG = 1, TGP_XCHG_BAD_OLD = 2, TGP_XCHG_BAD_DONOR = 3 };
+enum { TGP_XCHG_OLD_UNIFORM = 1, TGP_XCHG_NEW_UNIFORM = 2 };
+
+typedef struct tgp_exchange {
+  const int32_t* old_row;  /* device [B]; NULL: output b uses old tree b             */
+  const void* old_node;    /* device [B]; int32 k, or float32 u with OLD_UNIFORM     */
+  const int32_t* new_row;  /* device [B]; NULL: donor tree b                         */
+  const void* new_node;    /* device [B]; int32 j, or float32 u with NEW_UNIFORM;
+                              NULL (index mode only): node 0, the whole donor tree  */
+  int64_t B;               /* number of output trees, 0 <= B <= 2^31 - 1             */
+  int32_t max_len;         /* length limit, 1 <= max_len <= old->Lmax                */
+  int32_t flags;           /* TGP_XCHG_OLD_UNIFORM | TGP_XCHG_NEW_UNIFORM            */
+} tgp_exchange;
+
+/* Enqueue B subtree exchanges on `stream` (no allocation, no synchronisation;
+ * capturable). old and donor are populations as above (they may be the same
+ * population). Output: device float32 rows out_type/out_value/out_size
+ * [B][out_stride], out_stride >= old->Lmax, of which the first old->Lmax
+ * columns are written; they must not overlap any input. xstatus: optional
+ * device int32 [B] receiving the TGP_XCHG_* code of each output. Host-side
+ * argument errors return a negative status and enqueue nothing. */
+tgp_status tgp_subtree_exchange(const tgp_pop* old, const tgp_pop* donor, const tgp_exchange* x,
+                                float* out_type, float* out_value, float* out_size, int64_t out_stride,
+                                int32_t* xstatus, hipStream_t stream);
+
 /* Static description of a status code. */
 const char* tgp_status_str(tgp_status s);
 

@@ -3,15 +3,16 @@
 The device library libtgp.so (include/tgp.h) evaluates a population of
 expression trees in the paper's NaN-padded prefix encoding on every data
 point and reduces to one mean squared error per tree; it also produces
-multi-output predictions and gradients. This package is a thin binding:
+multi-output predictions and gradients, and builds the next population's
+trees by subtree exchange (crossover and mutation). This package is a thin binding:
 torch provides device memory and streams, the HIP kernels do all the work.
 """
 
 from ._lib import (  # noqa: F401
     MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT, FLAG_NO_TAIL_CHECK, TgpError, load,
-    status_str, LIB_PATH,
+    status_str, LIB_PATH, XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR,
 )
 from .api import (  # noqa: F401
     Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_multi_output, eval_mse_grad, autotune,
-    TreeMSE,
+    subtree_exchange, crossover, mutation, TreeMSE,
 )

@@ -23,8 +23,11 @@ FLAG_NO_TAIL_CHECK = 1
 
 # symbols the header declares; the CPU tests check that each one is exported
 EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output",
-           "tgp_eval_mse_grad", "tgp_autotune", "tgp_status_str", "tgp_op_cost", "tgp_profile",
-           "tgp_profile_read")
+           "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_status_str", "tgp_op_cost",
+           "tgp_profile", "tgp_profile_read")
+
+XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR = 0, 1, 2, 3
+XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM = 1, 2
 
 
 class TgpPop(ctypes.Structure):
@@ -45,6 +48,12 @@ class TgpCfg(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TgpExchange(ctypes.Structure):
+    _fields_ = [("old_row", ctypes.c_void_p), ("old_node", ctypes.c_void_p), ("new_row", ctypes.c_void_p),
+                ("new_node", ctypes.c_void_p), ("B", ctypes.c_int64), ("max_len", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
 
 class TgpError(RuntimeError):
@@ -82,6 +91,9 @@ def load():
     lib.tgp_eval_mse_grad.restype = i32
     lib.tgp_autotune.argtypes = [P(TgpPop), P(TgpData), i32, i32, P(TgpCfg), vp, ctypes.c_size_t, vp]
     lib.tgp_autotune.restype = i32
+    lib.tgp_subtree_exchange.argtypes = [P(TgpPop), P(TgpPop), P(TgpExchange), vp, vp, vp, ctypes.c_int64, vp,
+                                         vp]
+    lib.tgp_subtree_exchange.restype = i32
     lib.tgp_op_cost.argtypes = [i32, P(ctypes.c_double)]
     lib.tgp_op_cost.restype = i32
     lib.tgp_profile.argtypes = [i32]

@@ -12,10 +12,10 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import TgpCfg, TgpData, TgpPop, check
+from ._lib import TgpCfg, TgpData, TgpExchange, TgpPop, check
 
 __all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output",
-           "eval_mse_grad", "autotune", "TreeMSE"]
+           "eval_mse_grad", "autotune", "subtree_exchange", "crossover", "mutation", "TreeMSE"]
 
 
 def _dev(t, name, dtype=torch.float32):
@@ -240,6 +240,61 @@ def autotune(pop, X, Y, n_out=None, want_grad=False, ws=None, stream=None):
     check(lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d), d.n_out, int(bool(want_grad)), ctypes.byref(out),
                            wp, wn, _stream(stream)), "tgp_autotune")
     return out.as_dict()
+
+
+def _node_arg(t, name, B, uniform):
+    if t is None:
+        return None
+    _dev(t, name, torch.float32 if uniform else torch.int32)
+    if t.dim() != 1 or t.shape[0] != B or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D tensor of {B} entries")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def subtree_exchange(old, donor, old_node, new_node=None, old_row=None, new_row=None, max_len=None,
+                     old_uniform=False, new_uniform=False, out=None, status=None, stream=None):
+    """Batched subtree exchange (§III-B): output tree b replaces the subtree at node old_node[b] of
+    old tree old_row[b] (default b) by the subtree at node new_node[b] (default 0) of donor tree
+    new_row[b] (default b). Node tensors are int32 indices, or float32 uniforms in [0, 1) on a side
+    whose *_uniform flag is set. Returns (Population [B][old.Lmax], status int32 [B])."""
+    lib = _lib.load()
+    B = old_node.shape[0] if isinstance(old_node, torch.Tensor) else 0
+    flags = (_lib.XCHG_OLD_UNIFORM if old_uniform else 0) | (_lib.XCHG_NEW_UNIFORM if new_uniform else 0)
+    x = TgpExchange(None, _node_arg(old_node, "old_node", B, old_uniform), None,
+                    _node_arg(new_node, "new_node", B, new_uniform), B,
+                    old.Lmax if max_len is None else int(max_len), flags)
+    for name, r in (("old_row", old_row), ("new_row", new_row)):
+        if r is not None:
+            _dev(r, name, torch.int32)
+            if r.dim() != 1 or r.shape[0] != B or not r.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous 1-D int32 tensor of {B} entries")
+            setattr(x, name, r.data_ptr())
+    dev = old.type.device
+    if out is None:
+        out = Population(*(torch.empty((B, old.Lmax), dtype=torch.float32, device=dev) for _ in range(3)))
+    if status is None:
+        status = torch.empty((B,), dtype=torch.int32, device=dev)
+    op, dp, ob = old.abi(), donor.abi(), out.abi()
+    check(lib.tgp_subtree_exchange(ctypes.byref(op), ctypes.byref(dp), ctypes.byref(x),
+                                   ctypes.c_void_p(out.type.data_ptr()), ctypes.c_void_p(out.value.data_ptr()),
+                                   ctypes.c_void_p(out.size.data_ptr()), ob.row_stride,
+                                   ctypes.c_void_p(status.data_ptr()), _stream(stream)), "tgp_subtree_exchange")
+    return out, status
+
+
+def crossover(pop, mate, u_old, u_new, max_len=None, out=None, status=None, stream=None):
+    """One-point crossover (§III-B): child b takes tree b of pop and replaces a random node's subtree
+    by a random subtree of tree mate[b]; nodes are drawn on the device from the uniforms u_old,
+    u_new (float32 [P] in [0, 1))."""
+    return subtree_exchange(pop, pop, u_old, u_new, new_row=mate, max_len=max_len, old_uniform=True,
+                            new_uniform=True, out=out, status=status, stream=stream)
+
+
+def mutation(pop, new_trees, u_old, max_len=None, out=None, status=None, stream=None):
+    """Subtree mutation (§III-B): child b replaces a random node's subtree of tree b of pop by the
+    whole of new_trees' tree b; the node is drawn on the device from u_old (float32 [P])."""
+    return subtree_exchange(pop, new_trees, u_old, None, max_len=max_len, old_uniform=True, out=out,
+                            status=status, stream=stream)
 
 
 class TreeMSE(torch.autograd.Function):

@@ -101,6 +101,38 @@ def test_multi_output_and_plan_host_checks():
     assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d), 1, 0, None, None, 0, None) == _lib.TGP_E_ARG
 
 
+def call_xchg(old=None, don=None, B=4, max_len=64, flags=0, old_node=FAKE, new_node=None, outs=None,
+              out_stride=64, x=True):
+    lib = tgp.load()
+    old = pop(10, 64) if old is None else old
+    don = pop(10, 64) if don is None else don
+    outs = (FAKE * 64, FAKE * 128, FAKE * 192) if outs is None else outs
+    xx = _lib.TgpExchange(None, old_node, None, new_node, B, max_len, flags)
+    return lib.tgp_subtree_exchange(ctypes.byref(old) if old else None, ctypes.byref(don) if don else None,
+                                    ctypes.byref(xx) if x else None,
+                                    *(ctypes.c_void_p(o) if o else None for o in outs), out_stride, None, None)
+
+
+def test_subtree_exchange_host_checks():
+    assert call_xchg(x=False) == _lib.TGP_E_ARG
+    assert call_xchg(old=pop(P=-1)) == _lib.TGP_E_SHAPE
+    assert call_xchg(don=pop(Lmax=2048)) == _lib.TGP_E_UNSUPPORTED
+    assert call_xchg(old=pop(stride=10)) == _lib.TGP_E_SHAPE
+    assert call_xchg(B=-1) == _lib.TGP_E_SHAPE
+    assert call_xchg(flags=4) == _lib.TGP_E_ARG
+    assert call_xchg(max_len=0) == _lib.TGP_E_SHAPE
+    assert call_xchg(max_len=65) == _lib.TGP_E_SHAPE       # above the old rows' Lmax
+    assert call_xchg(old_node=None) == _lib.TGP_E_ARG
+    assert call_xchg(flags=2) == _lib.TGP_E_ARG            # uniform donor nodes need new_node
+    assert call_xchg(outs=(FAKE * 64, 0, FAKE * 192)) == _lib.TGP_E_ARG
+    assert call_xchg(out_stride=63) == _lib.TGP_E_SHAPE
+    # outputs overlapping an input or each other
+    assert call_xchg(outs=(FAKE, FAKE * 128, FAKE * 192)) == _lib.TGP_E_ARG
+    assert call_xchg(outs=(FAKE * 64, FAKE * 64 + 512, FAKE * 192)) == _lib.TGP_E_ARG
+    # nothing to do: no launch, whatever the pointers
+    assert call_xchg(B=0, old_node=None, outs=(0, 0, 0)) == _lib.TGP_OK
+
+
 def test_status_strings():
     for code in (0, -1, -2, -4, -5, -6, 7):
         s = tgp.status_str(code)
