@@ -16,7 +16,10 @@ Prints one JSON line. Extra objects:
                 per workgroup, fixed shape), the batched persistent queue
                 replayed as a captured hipGraph, and forward + adjoint
                 (fitness, d/d constants and d/dX), each in GPops/s and as a
-                ratio to the plain forward kernel.
+                ratio to the plain forward kernel;
+  exchange      the subtree-exchange kernel (§III-B) producing the next
+                population by one-point crossover, in children per second,
+                against the HBM bandwidth peak.
 """
 
 import argparse
@@ -35,6 +38,9 @@ METRIC = "GPops/s (tree nodes × points / s), fwd MSE and fwd+adjoint vs plain f
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "tanh", "exp", "log", "max", "min", "tan")
 EVAL_SOURCES = ("eval_impl.h", "interp.h", "tgp_isa.h", "tgp_kernels.h")
+XCHG_SOURCES = ("exchange.hip", "tgp_exchange.h")
+PEAK_HBM_GBS = 8000.0
+XCHG_MIN_CHILDREN = 200_000
 
 
 def parse():
@@ -53,24 +59,26 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-forward / batched-persistent graph / forward+adjoint comparison")
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
+    ap.add_argument("--no-exchange", action="store_true", help="skip the subtree-exchange measurement")
+    ap.add_argument("--exchange-steps", type=int, default=20)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to device once: a kernel of known "
                          "traffic for calibrating memory counters")
     return ap.parse_args()
 
 
-def eval_source_hash():
+def eval_source_hash(files=EVAL_SOURCES):
     h = hashlib.sha256()
-    for f in EVAL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2501_17168_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload, src_hash):
-    """HBM bytes per evaluation launch from the committed rocprofv3 --pmc summary, if it was
-    taken on the current evaluation-kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"eval_{workload}_traffic.md")
+def stored_traffic(workload, src_hash, kernel="eval"):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 --pmc summary, if it was
+    taken on the kernel's current source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -100,6 +108,52 @@ def timed_ms(torch, fn, steps, warmup=2):
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
 
+
+def exchange_bench(tgp, torch, w, workload, steps, warmup=3):
+    """One-point crossover (§III-B) producing the next population: parents are the workload's
+    trees repeated to at least XCHG_MIN_CHILDREN rows, child b = parent b with a random node's
+    subtree replaced by a random subtree of a random mate; nodes drawn on the device from
+    seeded uniforms. Two output modes: a fresh buffer (every column written) and a buffer that
+    already holds padded trees (only the changed columns written), the steady state when two
+    population buffers take turns. Timed with HIP events on the launch stream (the exchange
+    kernel is the only launch inside each timed region)."""
+    import numpy as np
+    reps = -(-XCHG_MIN_CHILDREN // w.P)
+    dev = torch.device("cuda:0")
+    par = tgp.Population(*(torch.from_numpy(a).to(dev).repeat(reps, 1).contiguous()
+                           for a in (w.type, w.value, w.size)))
+    B, L = par.P, par.Lmax
+    rng = np.random.default_rng(2025)
+    mate = torch.from_numpy(rng.integers(0, B, B).astype(np.int32)).to(dev)
+    u = torch.from_numpy(rng.random(B).astype(np.float32)).to(dev)
+    v = torch.from_numpy(rng.random(B).astype(np.float32)).to(dev)
+    out = tgp.Population(*(torch.empty((B, L), dtype=torch.float32, device=dev) for _ in range(3)))
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    full_ms = timed_ms(torch, lambda: tgp.crossover(par, mate, u, v, out=out, status=status), steps, warmup)
+    st = status.cpu().numpy()
+    child_len = out.size[:, 0].cpu().numpy().astype(np.int64)
+    # the same call into rows that hold the children already (steady state of two buffers)
+    pad_ms = timed_ms(torch, lambda: tgp.crossover(par, mate, u, v, out=out, out_padded=True, status=status),
+                      steps, warmup)
+    read = 12.0 * float(child_len.sum()) + 16.0 * B     # each child's nodes, mate row, two uniforms, status
+    full_bytes = 12.0 * B * L + read                      # every output column written
+    pad_bytes = 12.0 * float(child_len.sum()) + 4.0 * B + read   # the child's columns, plus its current length
+    src_hash = eval_source_hash(XCHG_SOURCES)
+
+    def roof(nbytes, ms, mode):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                "traffic": stored_traffic(f"{workload}_{mode}", src_hash, kernel="exchange"),
+                "kernel": "exchange_kernel", "kernel_ms": ms, "algo_bytes_per_launch": nbytes,
+                "exchange_source_hash": src_hash}
+
+    return {"workload": f"one-point crossover, {B:,} children from the {workload} trees repeated {reps}x "
+                        f"(Lmax {L}), nodes from seeded uniforms",
+            "value": B / (pad_ms * 1e-3), "unit": "trees/s", "mode": "padded output rows (two buffers in turn)",
+            "children": B, "exchanged": float(np.mean(st == 0)), "mean_child_len": float(child_len.mean()),
+            "padded": {"ms": pad_ms, "trees/s": B / (pad_ms * 1e-3), "roofline": roof(pad_bytes, pad_ms, "padded")},
+            "full_write": {"ms": full_ms, "trees/s": B / (full_ms * 1e-3),
+                           "roofline": roof(full_bytes, full_ms, "full")}}
 
 def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
     """Plain forward vs batched persistent (hipGraph replay) vs forward + adjoint on one workload."""
@@ -286,6 +340,7 @@ def main():
         del src, dst
 
     forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
+    exchange = None if args.no_exchange else exchange_bench(tgp, torch, w, args.workload, args.exchange_steps)
 
     # ---- roofline of the evaluation kernel ----
     if args.no_roofline:
@@ -313,7 +368,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
                       "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
-           "roofline": roofline, "cpu_baseline": cpu, "forms": forms}
+           "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "exchange": exchange}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -201,7 +201,12 @@ tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
  * gives for valid old and donor trees (tgp_plan status 0); for others only
  * the checks above are made. */
 enum { TGP_XCHG_OK = 0, TGP_XCHG_TOO_LONG = 1, TGP_XCHG_BAD_OLD = 2, TGP_XCHG_BAD_DONOR = 3 };
-enum { TGP_XCHG_OLD_UNIFORM = 1, TGP_XCHG_NEW_UNIFORM = 2 };
+/* TGP_XCHG_OUT_PADDED: the output rows already hold valid padded trees (for
+ * example the population of two generations back, when two buffers take
+ * turns); only the first max(new length, current length) columns of each
+ * row are written, which gives the same rows as a full write. A row whose
+ * current size[0] is not an integer in [1, old->Lmax] is written whole. */
+enum { TGP_XCHG_OLD_UNIFORM = 1, TGP_XCHG_NEW_UNIFORM = 2, TGP_XCHG_OUT_PADDED = 4 };
 
 typedef struct tgp_exchange {
   const int32_t* old_row;  /* device [B]; NULL: output b uses old tree b             */
@@ -211,7 +216,7 @@ typedef struct tgp_exchange {
                               NULL (index mode only): node 0, the whole donor tree  */
   int64_t B;               /* number of output trees, 0 <= B <= 2^31 - 1             */
   int32_t max_len;         /* length limit, 1 <= max_len <= old->Lmax                */
-  int32_t flags;           /* TGP_XCHG_OLD_UNIFORM | TGP_XCHG_NEW_UNIFORM            */
+  int32_t flags;           /* TGP_XCHG_OLD_UNIFORM | _NEW_UNIFORM | _OUT_PADDED      */
 } tgp_exchange;
 
 /* Enqueue B subtree exchanges on `stream` (no allocation, no synchronisation;

@@ -42,6 +42,9 @@ Readings (where the paper is silent):
   by NaN, which for a valid tree is the row itself.
 * The result is defined for valid old and donor trees (plan status 0).
   For other trees only the checks above are made.
+* Writing into output rows that already hold padded trees (the device
+  library's padded-output option) only skips rewriting NaN that is already
+  there; the rows are the same, so the oracle has no such option.
 """
 
 import math

@@ -27,7 +27,7 @@ EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_ou
            "tgp_profile", "tgp_profile_read")
 
 XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR = 0, 1, 2, 3
-XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM = 1, 2
+XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM, XCHG_OUT_PADDED = 1, 2, 4
 
 
 class TgpPop(ctypes.Structure):

@@ -252,14 +252,18 @@ def _node_arg(t, name, B, uniform):
 
 
 def subtree_exchange(old, donor, old_node, new_node=None, old_row=None, new_row=None, max_len=None,
-                     old_uniform=False, new_uniform=False, out=None, status=None, stream=None):
+                     old_uniform=False, new_uniform=False, out=None, out_padded=False, status=None, stream=None):
     """Batched subtree exchange (§III-B): output tree b replaces the subtree at node old_node[b] of
     old tree old_row[b] (default b) by the subtree at node new_node[b] (default 0) of donor tree
     new_row[b] (default b). Node tensors are int32 indices, or float32 uniforms in [0, 1) on a side
-    whose *_uniform flag is set. Returns (Population [B][old.Lmax], status int32 [B])."""
+    whose *_uniform flag is set. out_padded: `out` already holds valid padded trees, so only the
+    columns that change are written. Returns (Population [B][old.Lmax], status int32 [B])."""
     lib = _lib.load()
     B = old_node.shape[0] if isinstance(old_node, torch.Tensor) else 0
-    flags = (_lib.XCHG_OLD_UNIFORM if old_uniform else 0) | (_lib.XCHG_NEW_UNIFORM if new_uniform else 0)
+    if out_padded and out is None:
+        raise ValueError("out_padded needs an output population to write into")
+    flags = ((_lib.XCHG_OLD_UNIFORM if old_uniform else 0) | (_lib.XCHG_NEW_UNIFORM if new_uniform else 0)
+             | (_lib.XCHG_OUT_PADDED if out_padded else 0))
     x = TgpExchange(None, _node_arg(old_node, "old_node", B, old_uniform), None,
                     _node_arg(new_node, "new_node", B, new_uniform), B,
                     old.Lmax if max_len is None else int(max_len), flags)
@@ -272,6 +276,8 @@ def subtree_exchange(old, donor, old_node, new_node=None, old_row=None, new_row=
     dev = old.type.device
     if out is None:
         out = Population(*(torch.empty((B, old.Lmax), dtype=torch.float32, device=dev) for _ in range(3)))
+    elif out.P != B or out.Lmax < old.Lmax:
+        raise ValueError(f"out must hold {B} rows of at least {old.Lmax} columns")
     if status is None:
         status = torch.empty((B,), dtype=torch.int32, device=dev)
     op, dp, ob = old.abi(), donor.abi(), out.abi()
@@ -282,19 +288,19 @@ def subtree_exchange(old, donor, old_node, new_node=None, old_row=None, new_row=
     return out, status
 
 
-def crossover(pop, mate, u_old, u_new, max_len=None, out=None, status=None, stream=None):
+def crossover(pop, mate, u_old, u_new, max_len=None, out=None, out_padded=False, status=None, stream=None):
     """One-point crossover (§III-B): child b takes tree b of pop and replaces a random node's subtree
     by a random subtree of tree mate[b]; nodes are drawn on the device from the uniforms u_old,
     u_new (float32 [P] in [0, 1))."""
     return subtree_exchange(pop, pop, u_old, u_new, new_row=mate, max_len=max_len, old_uniform=True,
-                            new_uniform=True, out=out, status=status, stream=stream)
+                            new_uniform=True, out=out, out_padded=out_padded, status=status, stream=stream)
 
 
-def mutation(pop, new_trees, u_old, max_len=None, out=None, status=None, stream=None):
+def mutation(pop, new_trees, u_old, max_len=None, out=None, out_padded=False, status=None, stream=None):
     """Subtree mutation (§III-B): child b replaces a random node's subtree of tree b of pop by the
     whole of new_trees' tree b; the node is drawn on the device from u_old (float32 [P])."""
     return subtree_exchange(pop, new_trees, u_old, None, max_len=max_len, old_uniform=True, out=out,
-                            status=status, stream=stream)
+                            out_padded=out_padded, status=status, stream=stream)
 
 
 class TreeMSE(torch.autograd.Function):

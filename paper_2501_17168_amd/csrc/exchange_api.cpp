@@ -50,7 +50,7 @@ __attribute__((visibility("default"))) tgp_status tgp_subtree_exchange(
   if (!x) return TGP_E_ARG;
   if (x->B < 0) return TGP_E_SHAPE;
   if (x->B > kMaxRows) return TGP_E_UNSUPPORTED;
-  if (x->flags & ~(TGP_XCHG_OLD_UNIFORM | TGP_XCHG_NEW_UNIFORM)) return TGP_E_ARG;
+  if (x->flags & ~(TGP_XCHG_OLD_UNIFORM | TGP_XCHG_NEW_UNIFORM | TGP_XCHG_OUT_PADDED)) return TGP_E_ARG;
   if (x->max_len < 1 || x->max_len > old->Lmax) return TGP_E_SHAPE;
   if (x->B == 0) return TGP_OK;
   if (!x->old_node || !out_type || !out_value || !out_size) return TGP_E_ARG;

@@ -119,7 +119,7 @@ def test_subtree_exchange_host_checks():
     assert call_xchg(don=pop(Lmax=2048)) == _lib.TGP_E_UNSUPPORTED
     assert call_xchg(old=pop(stride=10)) == _lib.TGP_E_SHAPE
     assert call_xchg(B=-1) == _lib.TGP_E_SHAPE
-    assert call_xchg(flags=4) == _lib.TGP_E_ARG
+    assert call_xchg(flags=8) == _lib.TGP_E_ARG
     assert call_xchg(max_len=0) == _lib.TGP_E_SHAPE
     assert call_xchg(max_len=65) == _lib.TGP_E_SHAPE       # above the old rows' Lmax
     assert call_xchg(old_node=None) == _lib.TGP_E_ARG

@@ -184,3 +184,32 @@ def test_fullsize_crossover_and_graph_replay():
         for a, b in zip((got.type, got.value, got.size), ref):
             assert torch.equal(a.view(torch.int32), b.view(torch.int32))
         np.testing.assert_array_equal(gst.cpu().numpy(), st)
+
+
+@pytest.mark.parametrize("L", [64, 256, 1024])
+def test_padded_output_rows(L):
+    """With the output rows already holding padded trees, only the changed columns are written
+    and the rows equal those of a full write; rows whose current length is unreadable are
+    written whole."""
+    print(f"[exchange padded] L={L}", flush=True)
+    P = 500
+    pop = population(41 + L, P, L, depth=8 if L >= 256 else 5)
+    prev = population(42 + L, P, L, depth=9 if L >= 256 else 5)     # what the buffer held before
+    prev[2][:10, 0] = np.nan                                          # unreadable: written whole
+    for r in range(3):
+        prev[r][:10, L // 2:] = 7.0                                   # (its garbage must be overwritten)
+    rng = np.random.default_rng(L)
+    mate = rng.permutation(P)
+    u = rng.random(P).astype(np.float32)
+    w = rng.random(P).astype(np.float32)
+    want, wst = O.subtree_exchange(pop, pop, u, w, new_row=mate, flags=O.OLD_UNIFORM | O.NEW_UNIFORM)
+    dp = dev_pop(pop)
+    out = dev_pop(prev)
+    got, gst = tgp.crossover(dp, t_i32(mate), t_f32(u), t_f32(w), out=out, out_padded=True)
+    torch.cuda.synchronize()
+    assert got is out
+    assert_same(got, gst, want, wst, f"padded L={L}")
+    # again into the same rows (now holding the children): still the same result
+    got, gst = tgp.crossover(dp, t_i32(mate), t_f32(u), t_f32(w), out=out, out_padded=True)
+    torch.cuda.synchronize()
+    assert_same(got, gst, want, wst, f"padded again L={L}")
