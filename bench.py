@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
     ap.add_argument("--no-exchange", action="store_true", help="skip the subtree-exchange measurement")
     ap.add_argument("--exchange-steps", type=int, default=20)
+    ap.add_argument("--pagie-sweep", action="store_true",
+                    help="instead of the benchmark: the threshold study of §V-B (Pagie polynomial, populations "
+                         "100..10,000, D swept), every schedule timed, printed as one JSON line")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, copy this many MiB device to device once: a kernel of known "
                          "traffic for calibrating memory counters")
@@ -259,8 +262,98 @@ def cpu_baseline(w, seconds, max_workers=16):
     return res
 
 
+SWEEP_P = (100, 1_000, 5_000, 10_000)
+SWEEP_D = (256, 1_024, 4_096, 8_192, 16_384, 32_768, 65_536, 262_144)
+LANES = 256 * 64  # MI355X: 256 CUs x 64 lanes, the counterpart of the paper's CUDA-core count
+
+
+def _mode_grid(mode, V):
+    """Launch configurations tried per schedule in the threshold study."""
+    ks = [4, 8] + ([16] if V <= 2 else [])
+    if mode == 1:
+        return [dict(mode=1, points_per_lane=k, block_waves=b) for k in ks for b in (1, 2, 4)]
+    if mode == 2:
+        return [dict(mode=2, points_per_lane=k, block_waves=b, trees_per_unit=t)
+                for k in ks for b in (1, 4) for t in (1, 4, 16, 64)]
+    return [dict(mode=3, points_per_lane=k, block_waves=b, trees_per_unit=t, flags=f)
+            for k in ks for b in (1, 4) for t in (1, 2, 4) for f in (0, 2)]
+
+
+def pagie_sweep(steps=5):
+    """The threshold study of §V-B on this GPU: Pagie-polynomial populations of 100..10,000 trees,
+    D swept from 256 to 262,144. At each point every schedule is timed at its best launch
+    configuration from a small grid (HIP events): tree-major and persistent (the work unit is
+    a tree: parallelism from the population) and point-major (the work unit is a point tile
+    swept across a run of trees: parallelism from the data). The autotuner's choice is timed
+    too, and set beside the paper's rule, which moves to data parallelism once D reaches the
+    core count (here the lane count, 16,384)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2501_17168_amd as tgp
+
+    dev = torch.device("cuda:0")
+    names = {1: "tree-major", 2: "point-major", 3: "persistent"}
+    rows = []
+    for P in SWEEP_P:
+        w = synth.workload("pagie", P=P, D=max(SWEEP_D))
+        pop = tgp.Population(*(torch.from_numpy(a).to(dev) for a in (w.type, w.value, w.size)))
+        sum_len = int(w.lengths().sum())
+        for D in SWEEP_D:
+            X = torch.from_numpy(np.ascontiguousarray(w.X[:, :D])).to(dev)
+            Y = torch.from_numpy(np.ascontiguousarray(w.Y[:, :D])).to(dev)
+            ms, best_cfg = {}, {}
+            for mode, name in names.items():
+                for cand in _mode_grid(mode, w.V):
+                    c = tgp.cfg(cand)
+                    t = timed_ms(torch, lambda: tgp.eval_mse(pop, X, Y, config=c), steps, warmup=1)
+                    if name not in ms or t < ms[name]:
+                        ms[name], best_cfg[name] = t, cand
+            tuned = tgp.autotune(pop, X, Y)
+            ct = tgp.cfg(tuned)
+            ms["autotuned"] = timed_ms(torch, lambda: tgp.eval_mse(pop, X, Y, config=ct), steps)
+            # the same call replayed from a hipGraph: device time without the host's per-call cost
+            ws, out = tgp.Workspace(dev), torch.empty(P, device=dev)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                tgp.eval_mse(pop, X, Y, config=ct, ws=ws, out=out)
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                tgp.eval_mse(pop, X, Y, config=ct, ws=ws, out=out)
+            ms["autotuned_graph"] = timed_ms(torch, graph.replay, steps)
+            del graph
+            best = min(names.values(), key=ms.get)
+            pop_best = min(ms["tree-major"], ms["persistent"])
+            row = {"P": P, "D": D, "ms": {k: round(v, 5) for k, v in ms.items()},
+                   "GPops/s": {k: sum_len * D / (v * 1e-3) for k, v in ms.items()},
+                   "best": best, "data_over_population": pop_best / ms["point-major"],
+                   "rule": "point-major" if D >= LANES else "population", "tuned": tuned,
+                   "best_cfg": best_cfg}
+            rows.append(row)
+            print(f"P={P:6d} D={D:7d} " + " ".join(f"{k}={v * 1e3:8.1f}us" for k, v in ms.items())
+                  + f" best={best} tuned-mode={tuned['mode']}", file=sys.stderr, flush=True)
+    # crossovers per population: the first D from which the data-parallel schedule stays ahead
+    # of the tree-per-workgroup one (the paper's comparison), and of every population schedule
+    def first_ahead(P, key):
+        rs = [r for r in rows if r["P"] == P]
+        ahead = [key(r) > 1.0 for r in rs]
+        return next((rs[i]["D"] for i in range(len(rs)) if all(ahead[i:])), None)
+
+    cross_tree = {P: first_ahead(P, lambda r: r["ms"]["tree-major"] / r["ms"]["point-major"]) for P in SWEEP_P}
+    cross_all = {P: first_ahead(P, lambda r: r["data_over_population"]) for P in SWEEP_P}
+    print(json.dumps({"sweep": "pagie threshold (§V-B)", "lanes": LANES, "P": SWEEP_P, "D": SWEEP_D,
+                      "crossover_D_vs_tree_major": cross_tree, "crossover_D_vs_all_population": cross_all,
+                      "rows": rows}), flush=True)
+    return 0
+
 def main():
     args = parse()
+    if args.pagie_sweep:
+        return pagie_sweep()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)

@@ -87,6 +87,24 @@ int pend_slots_for(int Lmax) {
   return lg + 2;
 }
 
+int device_cus() {
+  static int cus = -1;
+  static std::mutex m;
+  std::lock_guard<std::mutex> g(m);
+  if (cus < 0) {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+      cus = p.multiProcessorCount;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Resident waves per CU the evaluation kernel holds (4 SIMDs x its occupancy by K).
+int resident_per_cu(int K) { return K >= 16 ? 8 : (K >= 8 ? 12 : 20); }
+
 // Fill unset fields of a launch configuration.
 tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_out, bool grad) {
   tgp_cfg c{};
@@ -116,26 +134,15 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
       const int64_t ngroups = (ntiles + c.block_waves - 1) / c.block_waves;
       c.trees_per_unit = (int)std::max<int64_t>(1, (pop->P * ngroups + 8191) / 8192);
     } else {
-      c.trees_per_unit = 8;
+      // persistent: group trees only when the chunks still fill every resident wave slot;
+      // a short queue of long chunks leaves lone waves exposed to program-fetch latency
+      const int64_t slots = (int64_t)device_cus() * resident_per_cu(c.points_per_lane);
+      c.trees_per_unit = (int)std::min<int64_t>(8, std::max<int64_t>(1, pop->P * ntiles / slots));
     }
   }
   return c;
 }
 
-int device_cus() {
-  static int cus = -1;
-  static std::mutex m;
-  std::lock_guard<std::mutex> g(m);
-  if (cus < 0) {
-    int dev = 0;
-    hipDeviceProp_t p;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
-      cus = p.multiProcessorCount;
-    else
-      cus = 256;
-  }
-  return cus;
-}
 
 // Enqueue prep + plan (+ order). Returns the plan-related pointers.
 tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
@@ -223,9 +230,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   } else if (c.mode == TGP_MODE_POINT_MAJOR) {
     grid = ((pop->P + ea.tpu - 1) / ea.tpu) * ea.ngroups;
   } else {
-    // resident waves per CU the kernel can hold (4 SIMDs x its occupancy by K)
-    const int per_cu = K >= 16 ? 8 : (K >= 8 ? 12 : 20);
-    const int64_t cap = (int64_t)device_cus() * per_cu;
+    const int64_t cap = (int64_t)device_cus() * resident_per_cu(K);
     const int64_t chunks = (pop->P + ea.tpu - 1) / ea.tpu;
     ea.wpt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap / ntiles, chunks));
     ea.dynamic = (c.flags & TGP_FLAG_STATIC_ORDER) ? 0 : 1;

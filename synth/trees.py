@@ -27,6 +27,7 @@ TYPE_MODI0 = 3
 ARITY = np.array([2, 2, 2, 2, 1, 1, 1, 1, 1, 2, 2, 1], dtype=np.int64)
 F4 = np.array([0, 1, 2, 3], dtype=np.int64)             # + - * protected-div
 F11 = np.arange(11, dtype=np.int64)                     # F4 + sin cos tanh exp log max min
+F7 = np.array([0, 1, 2, 3, 4, 5, 11], dtype=np.int64)   # the paper's SR set: + - * pdiv sin cos tan
 
 CONST_LO, CONST_HI = -5.0, 5.0
 

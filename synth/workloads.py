@@ -7,7 +7,8 @@ regression setting (populations of 100..1e6 trees, up to 512 nodes, 60 to
 1e5 data points, several input variables; §V-A, §V-C) and extend it.
 
 Target values: the 'plain' workload uses the closed form x^3 + x^2 + x plus
-noise, which is computed here. The other workloads use hidden expression
+noise, and 'pagie' the Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4) (the
+threshold study of §V-B); both are computed here. The other workloads use hidden expression
 trees; their targets are hidden(X) + noise, assembled by the caller from
 `hidden` and `noise` with the evaluator the caller owns (see
 `Workload.targets_from`).
@@ -46,6 +47,11 @@ WORKLOADS = {
              "8 vars N(0,1), 65,536 points, hidden full(4) tree + N(0,0.01)",
         P=50_000, Lmax=256, V=8, D=65_536, funcs="F11", shape=("ramped", 2, 8), x=("normal", 0.0, 1.0),
         target=("full", 4), sigma=0.01, n_out=1, seed=4, n_sample=100, const_cap=32),
+    "pagie": dict(
+        desc="Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4): trees ramped half-and-half depth 2..8, Lmax 512, "
+             "{+,-,*,pdiv,sin,cos,tan}, 2 vars U(-5,5), no noise",
+        P=10_000, Lmax=512, V=2, D=16_384, funcs="F7", shape=("ramped", 2, 8), x=("uniform", -5.0, 5.0),
+        target="pagie", sigma=0.0, n_out=1, seed=5, n_sample=None),
 }
 
 
@@ -122,7 +128,7 @@ def workload(name, P=None, D=None, seed=None):
     X = _draw_x(rng, r["x"], r["V"], D)
     hidden = None
     Y = None
-    if r["target"] != "poly3":
+    if r["target"] not in ("poly3", "pagie"):
         depth = r["target"][1]
         Lh = 2 ** (depth + 1)
         hidden = tr.depth_limited(rng, r["n_out"], depth, True, getattr(tr, r["funcs"]), r["V"], Lh)
@@ -130,6 +136,11 @@ def workload(name, P=None, D=None, seed=None):
     if r["target"] == "poly3":
         x = X[0].astype(np.float64)
         Y = ((x ** 3 + x ** 2 + x)[None, :] + noise.astype(np.float64)).astype(np.float32)
+    if r["target"] == "pagie":
+        x, y = X[0].astype(np.float64), X[1].astype(np.float64)
+        with np.errstate(divide="ignore"):
+            f = 1.0 / (1.0 + x ** -4) + 1.0 / (1.0 + y ** -4)
+        Y = (f[None, :] + noise.astype(np.float64)).astype(np.float32)
     n_sample = r.get("n_sample")
     lengths = S[:, 0].astype(np.int64)
     if n_sample is None or n_sample >= P:
