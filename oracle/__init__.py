@@ -20,3 +20,6 @@ from .exchange_oracle import (  # noqa: F401
     subtree_exchange, exchange_tree, ancestors, pick_node,
     X_OK, X_TOO_LONG, X_BAD_OLD, X_BAD_DONOR, OLD_UNIFORM, NEW_UNIFORM,
 )
+from .generate_oracle import (  # noqa: F401
+    generate, philox4x32_10, to_unit, GROW, FULL, RAMPED,
+)
