@@ -19,7 +19,9 @@ Prints one JSON line. Extra objects:
                 ratio to the plain forward kernel;
   exchange      the subtree-exchange kernel (§III-B) producing the next
                 population by one-point crossover, in children per second,
-                against the HBM bandwidth peak.
+                against the HBM bandwidth peak;
+  generation    random ramped half-and-half trees drawn on the device, in
+                trees per second, against the HBM bandwidth peak.
 """
 
 import argparse
@@ -39,6 +41,7 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "tanh", "exp", "log", "max", "min", "tan")
 EVAL_SOURCES = ("eval_impl.h", "interp.h", "tgp_isa.h", "tgp_kernels.h")
 XCHG_SOURCES = ("exchange.hip", "tgp_exchange.h")
+GEN_SOURCES = ("generate.hip", "tgp_generate.h")
 PEAK_HBM_GBS = 8000.0
 XCHG_MIN_CHILDREN = 200_000
 
@@ -61,6 +64,7 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
     ap.add_argument("--no-exchange", action="store_true", help="skip the subtree-exchange measurement")
     ap.add_argument("--exchange-steps", type=int, default=20)
+    ap.add_argument("--no-generation", action="store_true", help="skip the tree-generation measurement")
     ap.add_argument("--pagie-sweep", action="store_true",
                     help="instead of the benchmark: the threshold study of §V-B (Pagie polynomial, populations "
                          "100..10,000, D swept), every schedule timed, printed as one JSON line")
@@ -262,6 +266,31 @@ def cpu_baseline(w, seconds, max_workers=16):
     return res
 
 
+def generation_bench(tgp, torch, steps=20, warmup=3):
+    """Ramped half-and-half initialisation on the device: 200,000 trees, depth 2..8, the 11-op set,
+    2 variables, Lmax 256 (the hybrid workload's shape), Philox4x32-10 draws. Timed with HIP
+    events on the launch stream."""
+    import numpy as np
+    P, L, V = XCHG_MIN_CHILDREN, 256, 2
+    funcs = list(range(11))
+    dev = torch.device("cuda:0")
+    out = tgp.Population(*(torch.empty((P, L), dtype=torch.float32, device=dev) for _ in range(3)))
+    att = torch.empty(P, dtype=torch.int32, device=dev)
+    kw = dict(method="ramped", depth_min=2, depth_max=8, seed=7, out=out, attempts=att)
+    ms = timed_ms(torch, lambda: tgp.generate(P, L, V, funcs, **kw), steps, warmup)
+    lens = out.size[:, 0].cpu().numpy().astype(np.int64)
+    algo_bytes = 12.0 * P * L + 4.0 * P       # every column of every row, and the attempt counts
+    gbs = algo_bytes / (ms * 1e-3) / 1e9
+    return {"workload": f"ramped half-and-half, {P:,} trees, depth 2..8, 11 ops, {V} variables, Lmax {L}",
+            "value": P / (ms * 1e-3), "unit": "trees/s", "ms": ms, "mean_len": float(lens.mean()),
+            "nodes/s": float(lens.sum()) / (ms * 1e-3), "mean_attempts": float(att.float().mean().item()),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": gbs / PEAK_HBM_GBS,
+                         "traffic": stored_traffic("hybrid", eval_source_hash(GEN_SOURCES), kernel="generate"),
+                         "kernel": "generate_kernel", "kernel_ms": ms, "algo_bytes_per_launch": algo_bytes,
+                         "generate_source_hash": eval_source_hash(GEN_SOURCES)}}
+
+
 SWEEP_P = (100, 1_000, 5_000, 10_000)
 SWEEP_D = (256, 1_024, 4_096, 8_192, 16_384, 32_768, 65_536, 262_144)
 LANES = 256 * 64  # MI355X: 256 CUs x 64 lanes, the counterpart of the paper's CUDA-core count
@@ -434,6 +463,7 @@ def main():
 
     forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
     exchange = None if args.no_exchange else exchange_bench(tgp, torch, w, args.workload, args.exchange_steps)
+    generation = None if args.no_generation else generation_bench(tgp, torch)
 
     # ---- roofline of the evaluation kernel ----
     if args.no_roofline:
@@ -461,7 +491,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
                       "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
-           "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "exchange": exchange}
+           "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "exchange": exchange,
+           "generation": generation}
     print(json.dumps(out), flush=True)
     return 0
 

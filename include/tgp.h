@@ -230,6 +230,51 @@ tgp_status tgp_subtree_exchange(const tgp_pop* old, const tgp_pop* donor, const 
                                 float* out_type, float* out_value, float* out_size, int64_t out_stride,
                                 int32_t* xstatus, hipStream_t stream);
 
+/* ---- random tree generation ----
+ * Grow, full and ramped half-and-half initialisation, one tree per thread
+ * (the paper initialises one individual per GPU thread), written as padded
+ * rows (§III-A). Random numbers are Philox4x32-10 (Salmon et al., SC 2011)
+ * with counter (tree, attempt, position, 0) and key (seed low 32 bits,
+ * seed high 32 bits); the four words of one call serve one node, mapped to
+ * [0, 1) as (w >> 8) * 2^-24. Tree index = first_tree + row.
+ *
+ * Per tree: depth limit d and method are d_max and the configured method,
+ * or, for RAMPED, d_min + (tree / 2) mod (d_max - d_min + 1), full for even
+ * trees and grow for odd ones. Slots are filled in prefix order; a slot at
+ * depth h holds a function when h < d and (full, or h == 0, or u0 < p_func),
+ * else a terminal. A function's op is funcs[floor(u1 * n_funcs)]; a
+ * terminal is a constant lo + (hi - lo) * u2 (float32, separately rounded)
+ * when u1 < p_const, else variable floor(u2 * V). Products are float32 and
+ * indices are clamped to the last entry. A tree that outgrows Lmax is
+ * drawn again with the next attempt number; after attempts_per_depth
+ * failures at one depth limit the limit drops by one (depth 0 is a single
+ * terminal, which always fits). */
+enum { TGP_GEN_GROW = 0, TGP_GEN_FULL = 1, TGP_GEN_RAMPED = 2 };
+
+typedef struct tgp_gen_cfg {
+  int32_t method;              /* TGP_GEN_*                                            */
+  int32_t depth_min;           /* ramped only; 0 <= depth_min <= depth_max             */
+  int32_t depth_max;           /* <= 30                                                */
+  int32_t V;                   /* input variables, 1..16                               */
+  const int32_t* funcs;        /* HOST array of n_funcs distinct op ids (0..11)        */
+  int32_t n_funcs;             /* 1..12                                                */
+  float const_lo, const_hi;    /* constants drawn from [const_lo, const_hi), finite    */
+  float p_func;                /* < 0: default n_funcs / (n_funcs + V + 1) (float32)   */
+  float p_const;               /* < 0: default 1 / (V + 1) (float32)                   */
+  int32_t attempts_per_depth;  /* >= 1                                                 */
+  uint64_t seed;
+  int64_t first_tree;          /* >= 0, first_tree + P <= 2^32                         */
+} tgp_gen_cfg;
+
+/* Enqueue the generation of P trees on `stream` (no allocation, no
+ * synchronisation). out_type/out_value/out_size: device float32 rows
+ * [P][out_stride], first Lmax columns written (1 <= Lmax <= 1024,
+ * out_stride >= Lmax). attempts: optional device int32 [P], the number of
+ * attempts each tree took. Host-side argument errors return a negative
+ * status and enqueue nothing. */
+tgp_status tgp_generate(const tgp_gen_cfg* g, int64_t P, int32_t Lmax, float* out_type, float* out_value,
+                        float* out_size, int64_t out_stride, int32_t* attempts, hipStream_t stream);
+
 /* Static description of a status code. */
 const char* tgp_status_str(tgp_status s);
 

@@ -4,7 +4,7 @@ The device library libtgp.so (include/tgp.h) evaluates a population of
 expression trees in the paper's NaN-padded prefix encoding on every data
 point and reduces to one mean squared error per tree; it also produces
 multi-output predictions and gradients, and builds the next population's
-trees by subtree exchange (crossover and mutation). This package is a thin binding:
+trees by subtree exchange (crossover and mutation) and draws random trees. This package is a thin binding:
 torch provides device memory and streams, the HIP kernels do all the work.
 """
 
@@ -14,5 +14,5 @@ from ._lib import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_multi_output, eval_mse_grad, autotune,
-    subtree_exchange, crossover, mutation, TreeMSE,
+    subtree_exchange, crossover, mutation, generate, TreeMSE,
 )

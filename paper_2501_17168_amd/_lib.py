@@ -23,11 +23,12 @@ FLAG_NO_TAIL_CHECK = 1
 
 # symbols the header declares; the CPU tests check that each one is exported
 EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output",
-           "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_status_str", "tgp_op_cost",
+           "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_generate", "tgp_status_str", "tgp_op_cost",
            "tgp_profile", "tgp_profile_read")
 
 XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR = 0, 1, 2, 3
 XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM, XCHG_OUT_PADDED = 1, 2, 4
+GEN_GROW, GEN_FULL, GEN_RAMPED = 0, 1, 2
 
 
 class TgpPop(ctypes.Structure):
@@ -54,6 +55,14 @@ class TgpExchange(ctypes.Structure):
     _fields_ = [("old_row", ctypes.c_void_p), ("old_node", ctypes.c_void_p), ("new_row", ctypes.c_void_p),
                 ("new_node", ctypes.c_void_p), ("B", ctypes.c_int64), ("max_len", ctypes.c_int32),
                 ("flags", ctypes.c_int32)]
+
+
+class TgpGenCfg(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("depth_min", ctypes.c_int32), ("depth_max", ctypes.c_int32),
+                ("V", ctypes.c_int32), ("funcs", ctypes.POINTER(ctypes.c_int32)), ("n_funcs", ctypes.c_int32),
+                ("const_lo", ctypes.c_float), ("const_hi", ctypes.c_float), ("p_func", ctypes.c_float),
+                ("p_const", ctypes.c_float), ("attempts_per_depth", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("first_tree", ctypes.c_int64)]
 
 
 class TgpError(RuntimeError):
@@ -94,6 +103,8 @@ def load():
     lib.tgp_subtree_exchange.argtypes = [P(TgpPop), P(TgpPop), P(TgpExchange), vp, vp, vp, ctypes.c_int64, vp,
                                          vp]
     lib.tgp_subtree_exchange.restype = i32
+    lib.tgp_generate.argtypes = [P(TgpGenCfg), ctypes.c_int64, i32, vp, vp, vp, ctypes.c_int64, vp, vp]
+    lib.tgp_generate.restype = i32
     lib.tgp_op_cost.argtypes = [i32, P(ctypes.c_double)]
     lib.tgp_op_cost.restype = i32
     lib.tgp_profile.argtypes = [i32]

@@ -12,10 +12,10 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import TgpCfg, TgpData, TgpExchange, TgpPop, check
+from ._lib import TgpCfg, TgpData, TgpExchange, TgpGenCfg, TgpPop, check
 
 __all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output",
-           "eval_mse_grad", "autotune", "subtree_exchange", "crossover", "mutation", "TreeMSE"]
+           "eval_mse_grad", "autotune", "subtree_exchange", "crossover", "mutation", "generate", "TreeMSE"]
 
 
 def _dev(t, name, dtype=torch.float32):
@@ -301,6 +301,34 @@ def mutation(pop, new_trees, u_old, max_len=None, out=None, out_padded=False, st
     whole of new_trees' tree b; the node is drawn on the device from u_old (float32 [P])."""
     return subtree_exchange(pop, new_trees, u_old, None, max_len=max_len, old_uniform=True, out=out,
                             out_padded=out_padded, status=status, stream=stream)
+
+
+_METHODS = {"grow": _lib.GEN_GROW, "full": _lib.GEN_FULL, "ramped": _lib.GEN_RAMPED}
+
+
+def generate(P, Lmax, V, funcs, method="ramped", depth_min=2, depth_max=6, seed=0, const_range=(-5.0, 5.0),
+             p_func=None, p_const=None, attempts_per_depth=8, first_tree=0, out=None, attempts=None,
+             device="cuda", stream=None):
+    """Random trees (grow / full / ramped half-and-half) drawn on the device from Philox4x32-10
+    counters. funcs: op ids. p_func / p_const None: the library's defaults. Returns
+    (Population [P][Lmax], attempts int32 [P])."""
+    lib = _lib.load()
+    fl = (ctypes.c_int32 * len(funcs))(*[int(f) for f in funcs])
+    g = TgpGenCfg(_METHODS[method], int(depth_min), int(depth_max), int(V), fl, len(funcs),
+                  float(const_range[0]), float(const_range[1]), -1.0 if p_func is None else float(p_func),
+                  -1.0 if p_const is None else float(p_const), int(attempts_per_depth), int(seed) & (2**64 - 1),
+                  int(first_tree))
+    if out is None:
+        out = Population(*(torch.empty((P, Lmax), dtype=torch.float32, device=device) for _ in range(3)))
+    elif out.P != P or out.Lmax < Lmax:
+        raise ValueError(f"out must hold {P} rows of at least {Lmax} columns")
+    if attempts is None:
+        attempts = torch.empty((P,), dtype=torch.int32, device=out.type.device)
+    check(lib.tgp_generate(ctypes.byref(g), int(P), int(Lmax), ctypes.c_void_p(out.type.data_ptr()),
+                           ctypes.c_void_p(out.value.data_ptr()), ctypes.c_void_p(out.size.data_ptr()),
+                           out.abi().row_stride, ctypes.c_void_p(attempts.data_ptr()), _stream(stream)),
+          "tgp_generate")
+    return out, attempts
 
 
 class TreeMSE(torch.autograd.Function):

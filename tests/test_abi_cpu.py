@@ -133,6 +133,39 @@ def test_subtree_exchange_host_checks():
     assert call_xchg(B=0, old_node=None, outs=(0, 0, 0)) == _lib.TGP_OK
 
 
+def call_gen(P=10, Lmax=64, stride=64, outs=(FAKE * 64, FAKE * 128, FAKE * 192), **kw):
+    lib = tgp.load()
+    funcs = kw.pop("funcs", [0, 1, 2])
+    fl = (ctypes.c_int32 * len(funcs))(*funcs)
+    cfg = dict(method=2, depth_min=2, depth_max=6, V=2, funcs=fl, n_funcs=len(funcs), const_lo=-5.0,
+               const_hi=5.0, p_func=-1.0, p_const=-1.0, attempts_per_depth=8, seed=1, first_tree=0)
+    cfg.update(kw)
+    g = _lib.TgpGenCfg(**cfg)
+    return lib.tgp_generate(ctypes.byref(g), P, Lmax, *(ctypes.c_void_p(o) if o else None for o in outs),
+                            stride, None, None)
+
+
+def test_generate_host_checks():
+    assert tgp.load().tgp_generate(None, 1, 8, None, None, None, 8, None, None) == _lib.TGP_E_ARG
+    assert call_gen(P=-1) == _lib.TGP_E_SHAPE
+    assert call_gen(Lmax=0) == _lib.TGP_E_SHAPE
+    assert call_gen(stride=32) == _lib.TGP_E_SHAPE
+    assert call_gen(Lmax=2048, stride=2048) == _lib.TGP_E_UNSUPPORTED
+    assert call_gen(method=3) == _lib.TGP_E_ARG
+    assert call_gen(depth_min=5, depth_max=4) == _lib.TGP_E_ARG
+    assert call_gen(depth_max=31) == _lib.TGP_E_UNSUPPORTED
+    assert call_gen(V=0) == _lib.TGP_E_ARG
+    assert call_gen(funcs=[0, 12]) == _lib.TGP_E_ARG
+    assert call_gen(funcs=[1, 1]) == _lib.TGP_E_ARG
+    assert call_gen(const_lo=1.0, const_hi=1.0) == _lib.TGP_E_ARG
+    assert call_gen(const_hi=float("inf")) == _lib.TGP_E_ARG
+    assert call_gen(attempts_per_depth=0) == _lib.TGP_E_ARG
+    assert call_gen(first_tree=(1 << 32) - 5) == _lib.TGP_E_ARG      # counters beyond 32 bits
+    assert call_gen(p_func=float("nan")) == _lib.TGP_E_ARG
+    assert call_gen(outs=(FAKE, 0, FAKE)) == _lib.TGP_E_ARG
+    assert call_gen(P=0, outs=(0, 0, 0)) == _lib.TGP_OK
+
+
 def test_status_strings():
     for code in (0, -1, -2, -4, -5, -6, 7):
         s = tgp.status_str(code)
