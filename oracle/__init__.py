@@ -23,3 +23,4 @@ from .exchange_oracle import (  # noqa: F401
 from .generate_oracle import (  # noqa: F401
     generate, philox4x32_10, to_unit, GROW, FULL, RAMPED,
 )
+from .classify_oracle import accuracy, accuracy_bounds, classes  # noqa: F401
