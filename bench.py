@@ -21,7 +21,9 @@ Prints one JSON line. Extra objects:
                 population by one-point crossover, in children per second,
                 against the HBM bandwidth peak;
   generation    random ramped half-and-half trees drawn on the device, in
-                trees per second, against the HBM bandwidth peak.
+                trees per second, against the HBM bandwidth peak;
+  classification  argmax accuracy of multi-output trees on a Wine-shaped
+                data set (§V-D), in GPops/s.
 """
 
 import argparse
@@ -65,6 +67,7 @@ def parse():
     ap.add_argument("--no-exchange", action="store_true", help="skip the subtree-exchange measurement")
     ap.add_argument("--exchange-steps", type=int, default=20)
     ap.add_argument("--no-generation", action="store_true", help="skip the tree-generation measurement")
+    ap.add_argument("--no-classification", action="store_true", help="skip the classification measurement")
     ap.add_argument("--pagie-sweep", action="store_true",
                     help="instead of the benchmark: the threshold study of §V-B (Pagie polynomial, populations "
                          "100..10,000, D swept), every schedule timed, printed as one JSON line")
@@ -291,6 +294,26 @@ def generation_bench(tgp, torch, steps=20, warmup=3):
                          "generate_source_hash": eval_source_hash(GEN_SOURCES)}}
 
 
+def classification_bench(tgp, torch, steps=20, warmup=3):
+    """Classification fitness (§V-D): the Wine-shaped workload (5,000 multi-output trees, 13
+    features, 3 classes, 178 points), autotuned launch, timed with HIP events per call."""
+    import numpy as np
+    import synth
+    w = synth.workload("classify")
+    dev = torch.device("cuda:0")
+    pop = tgp.Population(*(torch.from_numpy(a).to(dev) for a in (w.type, w.value, w.size)))
+    X = torch.from_numpy(w.X).to(dev)
+    lab = torch.from_numpy(np.ascontiguousarray(w.Y[0])).to(dev)
+    cfg = tgp.autotune(pop, X, torch.zeros((w.n_out, w.D), device=dev), n_out=w.n_out)
+    c = tgp.cfg(cfg)
+    out = torch.empty(w.P, device=dev)
+    ms = timed_ms(torch, lambda: tgp.eval_accuracy(pop, X, lab, w.n_out, config=c, out=out), steps, warmup)
+    gpops = float(w.lengths().sum()) * w.D
+    acc = out.cpu().numpy()
+    return {"workload": f"classify: {w.desc}", "value": gpops / (ms * 1e-3), "unit": "GPops/s", "ms": ms,
+            "schedule": cfg, "mean_accuracy": float(np.nanmean(acc)), "best_accuracy": float(np.nanmax(acc))}
+
+
 SWEEP_P = (100, 1_000, 5_000, 10_000)
 SWEEP_D = (256, 1_024, 4_096, 8_192, 16_384, 32_768, 65_536, 262_144)
 LANES = 256 * 64  # MI355X: 256 CUs x 64 lanes, the counterpart of the paper's CUDA-core count
@@ -464,6 +487,7 @@ def main():
     forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
     exchange = None if args.no_exchange else exchange_bench(tgp, torch, w, args.workload, args.exchange_steps)
     generation = None if args.no_generation else generation_bench(tgp, torch)
+    classification = None if args.no_classification else classification_bench(tgp, torch)
 
     # ---- roofline of the evaluation kernel ----
     if args.no_roofline:
@@ -492,7 +516,7 @@ def main():
            "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
                       "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
            "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "exchange": exchange,
-           "generation": generation}
+           "generation": generation, "classification": classification}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -144,6 +144,17 @@ tgp_status tgp_eval_multi_output(const tgp_pop* pop, const tgp_data* data, const
                                  float* mse, float* pred, int64_t ldp, int32_t* tree_status,
                                  void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Classification fitness (the classification domain of §V-D; multi-output
+ * trees of §IV-C): data->n_out = C classes (2..4), and row 0 of data->Y
+ * holds each point's class label (a float32 integer in [0, C); other values
+ * never match). Tree t predicts class c(x) = the first index of the largest
+ * of its C outputs, a NaN output counting below every number, and
+ * accuracy[t] = (1/D) * #{p : c(x_p) == label_p}; NaN for an invalid tree.
+ * The argmax is taken on the float32 outputs. accuracy: device float32 [P].
+ * tree_status: optional device int32 [P]. */
+tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg, float* accuracy,
+                             int32_t* tree_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* Fitness and its gradient (not in the paper; reverse-mode sweep over the
  * prefix tree with subtree values recomputed, nothing stored per point).
  * grad_mse: optional device float32 [P], upstream dL/dmse_t (NULL = all ones).

@@ -22,7 +22,7 @@ MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT = 0, 1, 2, 3
 FLAG_NO_TAIL_CHECK = 1
 
 # symbols the header declares; the CPU tests check that each one is exported
-EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output",
+EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output", "tgp_eval_accuracy",
            "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_generate", "tgp_status_str", "tgp_op_cost",
            "tgp_profile", "tgp_profile_read")
 
@@ -95,6 +95,8 @@ def load():
     lib.tgp_eval_multi_output.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, ctypes.c_int64, vp, vp,
                                           ctypes.c_size_t, vp]
     lib.tgp_eval_multi_output.restype = i32
+    lib.tgp_eval_accuracy.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp, ctypes.c_size_t, vp]
+    lib.tgp_eval_accuracy.restype = i32
     lib.tgp_eval_mse_grad.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp, vp, vp, vp, ctypes.c_size_t,
                                       vp]
     lib.tgp_eval_mse_grad.restype = i32

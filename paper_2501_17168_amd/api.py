@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import TgpCfg, TgpData, TgpExchange, TgpGenCfg, TgpPop, check
 
-__all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output",
+__all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output", "eval_accuracy",
            "eval_mse_grad", "autotune", "subtree_exchange", "crossover", "mutation", "generate", "TreeMSE"]
 
 
@@ -170,6 +170,26 @@ def eval_mse(pop, X, y, config=None, ws=None, out=None, tree_status=None, stream
     check(lib.tgp_eval_mse(ctypes.byref(p), ctypes.byref(d), _cfgp(config), ctypes.c_void_p(mse.data_ptr()), stp,
                            wp, wn, _stream(stream)), "tgp_eval_mse")
     return mse
+
+
+def eval_accuracy(pop, X, labels, n_classes, config=None, ws=None, out=None, tree_status=None, stream=None):
+    """Classification accuracy of every tree: the argmax of its n_classes outputs against labels
+    (float32 [D] or [1][D] holding class ids). Returns float32 [P]."""
+    lib = _lib.load()
+    _dev(labels, "labels")
+    lab = labels.reshape(1, -1)
+    d, _ = _data(X, lab, 1)
+    d.n_out = int(n_classes)
+    p = pop.abi()
+    acc = torch.empty((pop.P,), dtype=torch.float32, device=X.device) if out is None else out
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), int(n_classes), 0)
+    if nbytes == 0:
+        raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_eval_accuracy")
+    wp, wn = _ws(ws, nbytes, X.device)
+    stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
+    check(lib.tgp_eval_accuracy(ctypes.byref(p), ctypes.byref(d), _cfgp(config), ctypes.c_void_p(acc.data_ptr()),
+                                stp, wp, wn, _stream(stream)), "tgp_eval_accuracy")
+    return acc
 
 
 def eval_multi_output(pop, X, Y=None, n_out=None, want_mse=True, want_pred=False, config=None, ws=None,

@@ -182,7 +182,7 @@ tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, 
 
 tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, int n_out, float* mse,
                    float* pred, int64_t ldp, int32_t* tree_status, void* ws, size_t ws_bytes,
-                   hipStream_t s) {
+                   hipStream_t s, int loss = kLossSquared) {
   tgp_status st = check_pop(pop);
   if (st) return st;
   st = check_data(d, mse != nullptr);
@@ -211,6 +211,8 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   ea.Y = mse ? d->Y : nullptr;
   ea.ldy = d->ldy;
   ea.n_out = n_out;
+  ea.ny = loss == kLossAccuracy ? 1 : n_out;
+  ea.loss = loss;
   ea.info = (const int32_t*)(w + L.info);
   ea.prog = (const uint2*)(w + L.prog);
   ea.pstride = prog_stride(pop->Lmax);
@@ -294,6 +296,16 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse(const tgp_pop* po
   if (!data) return TGP_E_ARG;
   if (data->n_out != 1) return TGP_E_SHAPE;
   return forward(pop, data, cfg, 1, mse, nullptr, 0, tree_status, ws, ws_bytes, stream);
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data,
+                                                                    const tgp_cfg* cfg, float* accuracy,
+                                                                    int32_t* tree_status, void* ws,
+                                                                    size_t ws_bytes, hipStream_t stream) {
+  if (!accuracy || !data || !data->Y) return TGP_E_ARG;
+  if (data->n_out < 2) return TGP_E_SHAPE;
+  return forward(pop, data, cfg, data->n_out, accuracy, nullptr, 0, tree_status, ws, ws_bytes, stream,
+                 kLossAccuracy);
 }
 
 __attribute__((visibility("default"))) tgp_status tgp_eval_multi_output(

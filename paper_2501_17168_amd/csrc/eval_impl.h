@@ -74,11 +74,11 @@ __device__ __forceinline__ void load_tile(const EvalArgs& a, Regs<K, VM, NO>& s,
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
-    const float* yr = a.Y ? a.Y + (int64_t)(o < a.n_out ? o : 0) * a.ldy : nullptr;
+    const float* yr = a.Y ? a.Y + (int64_t)(o < a.ny ? o : 0) * a.ldy : nullptr;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       const int64_t p = p0 + j * kWave;
-      ty.y[o][j] = (yr && o < a.n_out && p < a.D) ? yr[p] : 0.0f;
+      ty.y[o][j] = (yr && o < a.ny && p < a.D) ? yr[p] : 0.0f;
     }
   }
 }
@@ -103,7 +103,7 @@ __device__ __forceinline__ unsigned long long uniform64(uint2 v) {
 // lane is p0, starting from its already-loaded first program word. Between
 // the program and the reduction, `between()` runs (the next prefetch).
 //
-// Fitness reduction: squared residuals in float32, summed pairwise per lane
+// Fitness reduction (accuracy: hit counts, exact): squared residuals in float32, summed pairwise per lane
 // and over the wave by DPP (all terms non-negative: relative error below
 // (log2 K + 6) float32 ulp, under 6e-7), then added in float64 across
 // waves. If the float32 wave sum overflows, the tile is summed again in
@@ -152,6 +152,29 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
     }
   }
   if (!a.Y) return;
+  if (a.loss == kLossAccuracy) {
+    // class = first index of the largest output, NaN below every number; a hit when it
+    // equals the label (row 0 of Y). Counts are exact in float32.
+    float hits = 0.0f;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      float best = out_val(s, modi, 0, j);
+      int cls = 0;
+#pragma unroll
+      for (int o = 1; o < NO; ++o) {
+        const float v = out_val(s, modi, o, j);
+        if (o < a.n_out && (v > best || (best != best && v == v))) {
+          best = v;
+          cls = o;
+        }
+      }
+      const int64_t p = p0 + j * kWave;
+      hits += (p < a.D && (float)cls == ty.y[0][j]) ? 1.0f : 0.0f;
+    }
+    const float tot = wave_sum_f32(hits);
+    if (lane == 0) unsafeAtomicAdd(&a.acc[t], (double)tot);
+    return;
+  }
   float lane_sum = 0.0f;
 #pragma unroll
   for (int o = 0; o < NO; ++o) {

@@ -40,6 +40,10 @@ struct OrderArgs {
   int32_t* order;       // [P] tree headers (index | kHdr* flags), longest length bucket first
 };
 
+// Per-point fitness terms: squared error summed over the outputs, or 1 when
+// the argmax of the outputs equals the point's class label.
+constexpr int kLossSquared = 0, kLossAccuracy = 1;
+
 struct EvalArgs {
   const float* X;
   int64_t ldx;
@@ -48,6 +52,8 @@ struct EvalArgs {
   const float* Y;       // null in prediction-only mode
   int64_t ldy;
   int32_t n_out;
+  int32_t ny;           // rows of Y read: n_out (squared error) or 1 (class labels)
+  int32_t loss;         // kLossSquared or kLossAccuracy
   const int32_t* info;
   const uint2* prog;
   int64_t pstride;

@@ -7,8 +7,10 @@ regression setting (populations of 100..1e6 trees, up to 512 nodes, 60 to
 1e5 data points, several input variables; §V-A, §V-C) and extend it.
 
 Target values: the 'plain' workload uses the closed form x^3 + x^2 + x plus
-noise, and 'pagie' the Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4) (the
-threshold study of §V-B); both are computed here. The other workloads use hidden expression
+noise, 'pagie' the Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4) (the
+threshold study of §V-B), and 'classify' class labels (one row) from the
+argmax of random linear projections of X (the classification domain of
+§V-D); all are computed here. The other workloads use hidden expression
 trees; their targets are hidden(X) + noise, assembled by the caller from
 `hidden` and `noise` with the evaluator the caller owns (see
 `Workload.targets_from`).
@@ -47,6 +49,12 @@ WORKLOADS = {
              "8 vars N(0,1), 65,536 points, hidden full(4) tree + N(0,0.01)",
         P=50_000, Lmax=256, V=8, D=65_536, funcs="F11", shape=("ramped", 2, 8), x=("normal", 0.0, 1.0),
         target=("full", 4), sigma=0.01, n_out=1, seed=4, n_sample=100, const_cap=32),
+    "classify": dict(
+        desc="classification, Wine-shaped: 5,000 multi-output trees (Modi outputs for 3 classes), ramped "
+             "half-and-half depth 2..6, 11 ops, 13 vars N(0,1), 178 points, labels = argmax of 3 random "
+             "linear projections",
+        P=5_000, Lmax=256, V=13, D=178, funcs="F11", shape=("ramped", 2, 6), x=("normal", 0.0, 1.0),
+        target="linear_argmax", sigma=0.0, n_out=3, seed=6, n_sample=None, modi_frac=1.0),
     "pagie": dict(
         desc="Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4): trees ramped half-and-half depth 2..8, Lmax 512, "
              "{+,-,*,pdiv,sin,cos,tan}, 2 vars U(-5,5), no noise",
@@ -104,7 +112,8 @@ def _population(rng, r, P):
         depth = rng.integers(lo, hi + 1, P)
         full = (np.arange(P) % 2) == 0
         T, Vv, S = tr.depth_limited(rng, P, depth, full, funcs, r["V"], r["Lmax"], r.get("const_cap"))
-        return T, Vv, S, None
+        modi = tr.assign_modi(rng, T, r["n_out"], r["modi_frac"]) if r.get("modi_frac") else None
+        return T, Vv, S, modi
     if kind == "loguniform":
         lo, hi = r["shape"][1], r["shape"][2]
         L = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), P))).astype(np.int64)
@@ -128,7 +137,7 @@ def workload(name, P=None, D=None, seed=None):
     X = _draw_x(rng, r["x"], r["V"], D)
     hidden = None
     Y = None
-    if r["target"] not in ("poly3", "pagie"):
+    if r["target"] not in ("poly3", "pagie", "linear_argmax"):
         depth = r["target"][1]
         Lh = 2 ** (depth + 1)
         hidden = tr.depth_limited(rng, r["n_out"], depth, True, getattr(tr, r["funcs"]), r["V"], Lh)
@@ -136,6 +145,9 @@ def workload(name, P=None, D=None, seed=None):
     if r["target"] == "poly3":
         x = X[0].astype(np.float64)
         Y = ((x ** 3 + x ** 2 + x)[None, :] + noise.astype(np.float64)).astype(np.float32)
+    if r["target"] == "linear_argmax":
+        W = rng.normal(0.0, 1.0, size=(r["n_out"], r["V"]))
+        Y = np.argmax(W @ X.astype(np.float64), axis=0).astype(np.float32)[None, :]
     if r["target"] == "pagie":
         x, y = X[0].astype(np.float64), X[1].astype(np.float64)
         with np.errstate(divide="ignore"):
