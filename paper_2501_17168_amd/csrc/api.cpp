@@ -2,8 +2,8 @@
 //
 // Every evaluation call enqueues, on the caller's stream and without any
 // allocation or synchronisation:
-//   prep (zero the bucket counters and the work queue)
-//   -> plan (validate, plan figures, compile programs, zero accumulators)
+//   plan (validate, plan figures, compile programs, zero accumulators and,
+//         for the persistent schedule, the bucket counters and work queues)
 //   -> [order trees by length bucket, persistent mode only]
 //   -> evaluation kernel -> finalize (fitness and per-tree status).
 #include <hip/hip_runtime.h>
@@ -144,12 +144,12 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
 }
 
 
-// Enqueue prep + plan (+ order). Returns the plan-related pointers.
+// Enqueue plan (+ order). The plan kernel zeroes the ordering and queue
+// counters when the order is wanted; nothing else reads them.
 tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
                         const Layout& L, int32_t* out_info, int32_t* out_status, bool want_order,
                         hipStream_t s, bool want_adj = false, int64_t n_queues = 0) {
   int32_t* counters = (int32_t*)(ws + L.counters);
-  if (launch_prep(counters, (int)(64 + n_queues * kQueueStride), s) != hipSuccess) return TGP_E_HIP;
   PlanArgs pa{};
   pa.type = pop->type;
   pa.value = pop->value;
@@ -167,6 +167,8 @@ tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, 
   pa.adj = want_adj ? (uint32_t*)(ws + L.gwork) : nullptr;
   pa.out_info = out_info;
   pa.out_status = out_status;
+  pa.zero = want_order ? counters : nullptr;
+  pa.n_zero = want_order ? 64 + n_queues * kQueueStride : 0;
   if (launch_plan(pa, s) != hipSuccess) return TGP_E_HIP;
   if (want_order) {
     OrderArgs oa{};

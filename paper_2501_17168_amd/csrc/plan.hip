@@ -181,6 +181,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
   if (t >= a.P) return;
+  // the ordering and queue counters of this call: 64 per wave, read only by later kernels
+  for (int64_t z = t * kWave + lane; z < a.n_zero; z += a.P * kWave) a.zero[z] = 0;
   const float* trow = a.type + t * a.row_stride;
   const float* vrow = a.value + t * a.row_stride;
   const float* srow = a.size + t * a.row_stride;
@@ -599,11 +601,6 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   }
 }
 
-__global__ void prep_kernel(int32_t* c, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) c[i] = 0;
-}
-
 // Counting sort of the trees by length bucket, longest bucket first,
 // invalid trees last. Two kernels of 256 trees per workgroup; each
 // workgroup aggregates its counts in LDS and issues one global atomic per
@@ -651,11 +648,6 @@ __global__ __launch_bounds__(kOrderBlock) void order_kernel(OrderArgs a) {
   }
   __syncthreads();
   if (k >= 0) a.order[base[k] + rank] = a.info[t * kInfoStride + kInfoHdr];
-}
-
-hipError_t launch_prep(int32_t* counters, int n, hipStream_t s) {
-  prep_kernel<<<(n + 255) / 256, 256, 0, s>>>(counters, n);
-  return hipGetLastError();
 }
 
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {

@@ -25,6 +25,8 @@ struct PlanArgs {
   uint32_t* adj;        // optional [P][Lmax][kAdjWords] adjoint records
   int32_t* out_info;    // optional [P][6]
   int32_t* out_status;  // optional [P]
+  int32_t* zero;        // optional counters the plan zeroes (their readers run after it)
+  int64_t n_zero;
 };
 
 // persistent work queues: one counter per point tile, each in its own
@@ -106,7 +108,6 @@ struct FinalArgs {
 };
 
 // launchers (defined in plan.hip / eval.hip)
-hipError_t launch_prep(int32_t* counters, int n, hipStream_t s);
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
 hipError_t launch_order(const OrderArgs& a, hipStream_t s);
 hipError_t launch_eval(const EvalArgs& a, int K, int VM, int NO, bool pred, int block_waves,
