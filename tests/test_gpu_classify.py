@@ -70,3 +70,20 @@ def test_fullsize_wine_shaped_autotuned():
     cfg = tgp.autotune(pop, torch.from_numpy(w.X).to(DEV), torch.from_numpy(np.zeros((3, w.D), np.float32)).to(DEV),
                        n_out=3)
     check(w, w.Y[0], 3, cfg, "classify full size")
+
+
+def test_status_output_and_host_checks():
+    """tree_status matches the plan's status codes; a single class is refused on the host."""
+    w = synth.workload("classify", P=64)
+    S = w.size.copy()
+    S[3, 0] = np.nan
+    pop = tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (w.type, w.value, S)))
+    X = torch.from_numpy(w.X).to(DEV)
+    lab = torch.from_numpy(np.ascontiguousarray(w.Y[0])).to(DEV)
+    st = torch.empty(64, dtype=torch.int32, device=DEV)
+    acc = tgp.eval_accuracy(pop, X, lab, 3, tree_status=st).cpu().numpy()
+    info = O.plan(w.type, w.value, S, w.V, 3)
+    np.testing.assert_array_equal(st.cpu().numpy(), info[:, 0])
+    assert np.isnan(acc[3]) and np.isfinite(np.delete(acc, 3)).all()
+    with pytest.raises(tgp.TgpError):
+        tgp.eval_accuracy(pop, X, lab, 1)

@@ -213,3 +213,37 @@ def test_padded_output_rows(L):
     got, gst = tgp.crossover(dp, t_i32(mate), t_f32(u), t_f32(w), out=out, out_padded=True)
     torch.cuda.synchronize()
     assert_same(got, gst, want, wst, f"padded again L={L}")
+
+
+def test_strided_rows_and_wider_donor():
+    """Old rows as a view of a wider tensor (row stride > Lmax), donors with 512-column rows
+    into 256-column outputs (long donor subtrees are refused by the length limit), and an
+    output population whose rows are a strided view too."""
+    P, L, Ld = 700, 256, 512
+    old = population(51, P, L, depth=8)
+    don = population(52, P, Ld, depth=9)
+    rng = np.random.default_rng(8)
+    u = rng.random(P).astype(np.float32)
+    w = rng.random(P).astype(np.float32)
+    mate = rng.permutation(P)
+    want, wst = O.subtree_exchange(old, don, u, w, new_row=mate, flags=O.OLD_UNIFORM | O.NEW_UNIFORM)
+
+    def wide(rows, L, extra):
+        out = []
+        for r in rows:
+            t = torch.full((r.shape[0], L + extra), 7.0, device=DEV)
+            t[:, :L] = torch.from_numpy(r).to(DEV)
+            out.append(t[:, :L])
+        return tgp.Population(*out)
+
+    dold, ddon = wide(old, L, 9), wide(don, Ld, 3)
+    assert dold.abi().row_stride == L + 9
+    outs = [torch.full((P, L + 5), -3.0, device=DEV) for _ in range(3)]
+    out = tgp.Population(*(t[:, :L] for t in outs))
+    got, gst = tgp.subtree_exchange(dold, ddon, t_f32(u), t_f32(w), new_row=t_i32(mate), old_uniform=True,
+                                    new_uniform=True, out=out)
+    torch.cuda.synchronize()
+    assert_same(got, gst, want, wst, "strided")
+    assert (wst == O.X_TOO_LONG).sum() > 0
+    for t in outs:                                   # the columns past Lmax are untouched
+        assert (t[:, L:] == -3.0).all()

@@ -88,3 +88,17 @@ def test_fullsize_sample_and_graph_replay():
         torch.cuda.synchronize()
         for a, b in zip((got.type, got.value, got.size), ref):
             assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_strided_output_rows():
+    """Generation into a row-strided view writes the first Lmax columns of each row only."""
+    P, L = 333, 64
+    want, watt = G.generate(P, L, 2, F7, method=G.RAMPED, d_min=1, d_max=5, seed=77)
+    outs = [torch.full((P, L + 11), 5.0, device=DEV) for _ in range(3)]
+    out = tgp.Population(*(t[:, :L] for t in outs))
+    got, att = tgp.generate(P, L, 2, F7, method="ramped", depth_min=1, depth_max=5, seed=77, out=out)
+    torch.cuda.synchronize()
+    same(got, want, "strided")
+    np.testing.assert_array_equal(att.cpu().numpy(), watt)
+    for t in outs:
+        assert (t[:, L:] == 5.0).all()
