@@ -171,8 +171,11 @@ tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp
 
 /* Time the candidate launch configurations on this population and data,
  * keep the fastest in a process-wide cache keyed by the shape, and return
- * it in *out. Synchronises the stream; not capturable. want_grad selects
- * the gradient path (reserved; forward configurations are tuned). */
+ * it in *out. Synchronises the stream; not capturable. With want_grad the
+ * gradient call is tuned instead (its workgroup shape and trees per unit;
+ * n_out must be 1, and the workspace sized with want_grad), and later
+ * tgp_eval_mse_grad calls on this shape with a NULL or AUTO cfg use it.
+ * Allocates and frees temporary device buffers. */
 tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
                         int32_t want_grad, tgp_cfg* out, void* ws, size_t ws_bytes,
                         hipStream_t stream);

@@ -333,9 +333,15 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (pop->P == 0) return TGP_OK;
   tgp_cfg c{};
   if (cfg) c = *cfg;
+  if (!cfg || c.mode == TGP_MODE_AUTO) {
+    tgp_cfg cached{};
+    if (autotune_lookup(pop, data, 1, true, &cached)) c = cached;
+  }
   c.mode = TGP_MODE_POINT_MAJOR;
   c.points_per_lane = 4;
-  if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 4;
+  // one wave per workgroup by default: the adjoint's LDS (spill slots and pending stack) bounds
+  // residency, and small workgroups pack it best
+  if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 1;
   char* w = (char*)ws;
   st = enqueue_plan(pop, data->V, 1, c, w, L, nullptr, nullptr, false, stream, true);
   if (st) return st;
@@ -347,8 +353,9 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   const int64_t tile = 64LL * K;
   const int64_t ntiles = (data->D + tile - 1) / tile;
   const int64_t ngroups = (ntiles + bw - 1) / bw;
+  // trees per unit: enough units for about 64 resident waves per CU, at most 64 trees per unit
   int64_t tpu = c.trees_per_unit;
-  if (tpu < 1) tpu = std::max<int64_t>(1, (pop->P * ngroups + 2047) / 2048);
+  if (tpu < 1) tpu = std::min<int64_t>(64, std::max<int64_t>(1, pop->P * ntiles / ((int64_t)device_cus() * 64)));
   AdjArgs aa{};
   aa.X = data->X;
   aa.ldx = data->ldx;
@@ -396,10 +403,11 @@ __attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* po
   if (st) return st;
   st = check_data(data, true);
   if (st) return st;
+  if (want_grad && n_out != 1) return TGP_E_SHAPE;
   const Layout L = layout(pop->P, pop->Lmax, want_grad ? grad_work_bytes(pop, data) : 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
-  return autotune_run(pop, data, n_out, out, ws, ws_bytes, stream);
+  return autotune_run(pop, data, n_out, want_grad != 0, out, ws, ws_bytes, stream);
 }
 
 __attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) {

@@ -8,8 +8,9 @@ namespace tgp {
 // Cached configuration for this shape, if any.
 bool autotune_lookup(const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, tgp_cfg* out);
 
-// Time the candidates on the caller's data (synchronises `s`), cache and return the fastest.
-tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, tgp_cfg* out, void* ws,
+// Time the candidates on the caller's data (synchronises `s`), cache and return the fastest:
+// forward schedules, or with `grad` the gradient call's workgroup shape and trees per unit.
+tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, tgp_cfg* out, void* ws,
                         size_t ws_bytes, hipStream_t s);
 
 }  // namespace tgp

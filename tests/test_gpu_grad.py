@@ -163,3 +163,27 @@ def test_graph_replay_matches_eager():
         got = out.cpu().numpy()
         np.testing.assert_allclose(got, eager, rtol=1e-6, atol=0, equal_nan=True)
         _ = tgp.eval_mse(pop, X, Yd, config=tgp.cfg(mode=1), ws=tgp.Workspace(DEV))   # eager work between replays
+
+
+@pytest.mark.parametrize("cfg", [dict(block_waves=1, trees_per_unit=1), dict(block_waves=2, trees_per_unit=4),
+                                 dict(block_waves=4, trees_per_unit=64), "tuned"])
+def test_grad_launch_shapes_agree(cfg):
+    """Every workgroup shape and trees-per-unit choice of the gradient call, and the autotuned one
+    (tgp_autotune with want_grad, then a call without a configuration), give the default call's
+    fitness and gradients up to the order of the atomic sums."""
+    w, Y = work("grad", P=400, D=3100)
+    pop = dev_pop(w)
+    X = torch.from_numpy(w.X).to(DEV)
+    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
+    ref = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd)]
+    if cfg == "tuned":
+        tuned = tgp.autotune(pop, X, Yd, want_grad=True)
+        print(f"tuned gradient launch: {tuned}", flush=True)
+        assert tuned["mode"] == 2 and tuned["points_per_lane"] == 4
+        got = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd)]
+    else:
+        got = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, **cfg))]
+    torch.cuda.synchronize()
+    for name, a, b in zip(("mse", "grad_value", "grad_X"), got, ref):
+        scale = np.nanmax(np.abs(b))
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6 * scale, equal_nan=True, err_msg=name)
