@@ -204,11 +204,14 @@ def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
     del g
 
     if w.n_out == 1:
+        # the gradient call's own launch shape, tuned like the forward's (later calls use it)
+        adj_cfg = tgp.autotune(pop, X, Y, want_grad=True, ws=ws)
+
         def fwd_adj():
             tgp.eval_mse_grad(pop, X, Y, ws=ws)
 
         ms_adj = timed_ms(torch, fwd_adj, steps)
-        res["fwd_adjoint"] = {"outputs": "fitness, d/d constants, d/dX", "ms": ms_adj,
+        res["fwd_adjoint"] = {"outputs": "fitness, d/d constants, d/dX", "cfg": adj_cfg, "ms": ms_adj,
                               "GPops/s": gpops_per_step / (ms_adj * 1e-3), "vs_plain_fwd": ms_plain / ms_adj}
     return res
 
