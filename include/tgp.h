@@ -163,7 +163,9 @@ tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp
  *   invalid trees).
  * grad_X: optional device float32 [V][ldx], overwritten with
  *   sum_t dL/dmse_t * dmse_t/dX.
- * n_out must be 1. mse: device float32 [P]. */
+ * n_out must be 1. mse: device float32 [P]. cfg: mode is ignored (the sweep
+ * is point-major); points_per_lane 2 or 4 (anything else: 4), block_waves
+ * and trees_per_unit as for the forward calls. */
 tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
                              const float* grad_mse, float* mse, float* grad_value,
                              float* grad_X, int32_t* tree_status, void* ws, size_t ws_bytes,
@@ -172,7 +174,8 @@ tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp
 /* Time the candidate launch configurations on this population and data,
  * keep the fastest in a process-wide cache keyed by the shape, and return
  * it in *out. Synchronises the stream; not capturable. With want_grad the
- * gradient call is tuned instead (its workgroup shape and trees per unit;
+ * gradient call is tuned instead (its points per lane, 2 or 4, workgroup
+ * shape and trees per unit;
  * n_out must be 1, and the workspace sized with want_grad), and later
  * tgp_eval_mse_grad calls on this shape with a NULL or AUTO cfg use it.
  * Allocates and frees temporary device buffers. */

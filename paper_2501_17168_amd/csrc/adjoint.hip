@@ -9,8 +9,15 @@ template <int K, int VM>
 hipError_t launch_adjoint_kv(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s);
 
 hipError_t launch_adjoint(const AdjArgs& a, int K, int VM, int block_waves, int64_t grid, hipStream_t s) {
-  (void)K;
   if (grid <= 0) return hipSuccess;
+  if (K == 2) {
+    switch (VM) {
+      case 2: return launch_adjoint_kv<2, 2>(a, block_waves, grid, s);
+      case 4: return launch_adjoint_kv<2, 4>(a, block_waves, grid, s);
+      case 8: return launch_adjoint_kv<2, 8>(a, block_waves, grid, s);
+      default: return launch_adjoint_kv<2, 16>(a, block_waves, grid, s);
+    }
+  }
   switch (VM) {
     case 2: return launch_adjoint_kv<4, 2>(a, block_waves, grid, s);
     case 4: return launch_adjoint_kv<4, 4>(a, block_waves, grid, s);

@@ -338,7 +338,8 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
     if (autotune_lookup(pop, data, 1, true, &cached)) c = cached;
   }
   c.mode = TGP_MODE_POINT_MAJOR;
-  c.points_per_lane = 4;
+  // 2 or 4 points per lane: at 2 the adjoint's registers and LDS halve and twice the waves fit
+  c.points_per_lane = c.points_per_lane == 2 ? 2 : 4;
   // one wave per workgroup by default: the adjoint's LDS (spill slots and pending stack) bounds
   // residency, and small workgroups pack it best
   if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 1;
@@ -348,7 +349,7 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (launch_zero_f32(grad_value, pop->P, pop->row_stride, pop->row_stride, stream) != hipSuccess) return TGP_E_HIP;
   if (launch_zero_f32(grad_X, data->V, data->D, data->ldx, stream) != hipSuccess) return TGP_E_HIP;
 
-  const int K = 4;
+  const int K = c.points_per_lane;
   const int bw = c.block_waves;
   const int64_t tile = 64LL * K;
   const int64_t ntiles = (data->D + tile - 1) / tile;

@@ -7,8 +7,8 @@
 // lane x waves per workgroup x trees per unit) is timed on the caller's own
 // population and data, and the fastest is cached under the shape key
 // (P, Lmax, V, D, n_out, gradient flag) for the rest of the process. The
-// gradient call has one schedule (point-major, 4 points per lane); its
-// candidates are the workgroup shape and the trees per unit.
+// gradient call has one schedule (point-major); its candidates are the
+// points per lane (2 or 4), the workgroup shape and the trees per unit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,8 +70,9 @@ tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, bool g
   };
   std::vector<tgp_cfg> cands;
   if (grad) {
-    for (int bw : {1, 2, 4})
-      for (int tpu : {1, 4, 16, 64}) cands.push_back(tgp_cfg{TGP_MODE_POINT_MAJOR, bw, 4, tpu, 0});
+    for (int k : {4, 2})
+      for (int bw : {1, 2})
+        for (int tpu : {1, 4, 16, 64}) cands.push_back(tgp_cfg{TGP_MODE_POINT_MAJOR, bw, k, tpu, 0});
   } else {
     for (int k : {16, 8, 4}) {
       if (k == 16 && d->V > 2) continue;

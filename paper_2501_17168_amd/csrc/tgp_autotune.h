@@ -9,7 +9,8 @@ namespace tgp {
 bool autotune_lookup(const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, tgp_cfg* out);
 
 // Time the candidates on the caller's data (synchronises `s`), cache and return the fastest:
-// forward schedules, or with `grad` the gradient call's workgroup shape and trees per unit.
+// forward schedules, or with `grad` the gradient call's points per lane, workgroup shape and trees
+// per unit.
 tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, tgp_cfg* out, void* ws,
                         size_t ws_bytes, hipStream_t s);
 
