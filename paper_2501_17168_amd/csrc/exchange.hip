@@ -66,19 +66,19 @@ struct Hdr {
   int64_t nshift;  // donor element of output column p is nshift + p
 };
 
-// The loads come in three rounds, each issued before anything waits on it:
+// The loads come in three passes, each issued before anything waits on it:
 // the per-output arguments (rows, node arguments), then the two trees'
 // lengths, then the sizes at the two chosen nodes. The checks run after.
 __device__ Hdr header(const XchgArgs& a, int64_t b) {
   const float nan = __builtin_nanf("");
-  // round 1
+  // loads, first pass: the per-output arguments
   const int orow = a.old_row ? a.old_row[b] : (int)b;
   const int nrow = a.new_row ? a.new_row[b] : (int)b;
   const int32_t kraw = ((const int32_t*)a.old_node)[b];
   const int32_t jraw = a.new_node ? ((const int32_t*)a.new_node)[b] : 0;
   const bool padded = a.flags & TGP_XCHG_OUT_PADDED;
   const float prev = padded ? a.out_s[b * a.out_ld] : nan;  // current length of a padded output row
-  // round 2
+  // loads, second pass: the two trees' lengths
   const bool orow_ok = orow >= 0 && (int64_t)orow < a.old_P;
   const bool nrow_ok = nrow >= 0 && (int64_t)nrow < a.new_P;
   const int64_t obase = orow_ok ? (int64_t)orow * a.old_ld : 0;
@@ -100,7 +100,7 @@ __device__ Hdr header(const XchgArgs& a, int64_t b) {
     }
   }
   const bool j_in = j >= 0 && j < a.Ln;
-  // round 3
+  // loads, third pass: the sizes at the two chosen nodes
   const float szk = k_in ? a.os[obase + k] : nan;
   const float szj = j_in ? a.ns[nbase + j] : nan;
 
