@@ -166,6 +166,27 @@ def test_generate_host_checks():
     assert call_gen(P=0, outs=(0, 0, 0)) == _lib.TGP_OK
 
 
+def test_accuracy_and_gradient_tuning_host_checks():
+    lib = tgp.load()
+    p = pop()
+    acc = ctypes.c_void_p(FAKE)
+    ws = ctypes.c_void_p(FAKE * 16)
+    d1 = data(n_out=1)
+    assert lib.tgp_eval_accuracy(ctypes.byref(p), ctypes.byref(d1), None, acc, None, ws, 1 << 40,
+                                 None) == _lib.TGP_E_SHAPE             # one class
+    d0 = data(n_out=3, Y=0)
+    assert lib.tgp_eval_accuracy(ctypes.byref(p), ctypes.byref(d0), None, acc, None, ws, 1 << 40,
+                                 None) == _lib.TGP_E_ARG               # no labels
+    d3 = data(n_out=3)
+    assert lib.tgp_eval_accuracy(ctypes.byref(p), ctypes.byref(d3), None, None, None, ws, 1 << 40,
+                                 None) == _lib.TGP_E_ARG               # no output
+    out = _lib.TgpCfg()
+    assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d3), 3, 1, ctypes.byref(out), ws, 1 << 40,
+                            None) == _lib.TGP_E_SHAPE                  # gradients need one output
+    assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d1), 1, 1, ctypes.byref(out), ws, 64,
+                            None) == _lib.TGP_E_WORKSPACE              # gradient workspace too small
+
+
 def test_status_strings():
     for code in (0, -1, -2, -4, -5, -6, 7):
         s = tgp.status_str(code)
