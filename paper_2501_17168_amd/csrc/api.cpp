@@ -81,10 +81,14 @@ int64_t grad_work_bytes(const tgp_pop* pop, const tgp_data* d) {
   return (int64_t)pop->P * pop->Lmax * kAdjWords * (int64_t)sizeof(uint32_t);
 }
 
+// Pending-stack slots of the adjoint sweep: the sweep descends into the
+// smaller child of a node with two function children and parks the larger,
+// so the k-th parked entry sits at a node of at least 5 nodes inside a
+// subtree of at most len / 2^(k-1): k <= floor(log2 len) <= floor(log2 Lmax).
 int pend_slots_for(int Lmax) {
   int lg = 0;
   while ((1 << (lg + 1)) <= Lmax) ++lg;
-  return lg + 2;
+  return std::max(1, lg);
 }
 
 int device_cus() {
