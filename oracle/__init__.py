@@ -24,3 +24,4 @@ from .generate_oracle import (  # noqa: F401
     generate, philox4x32_10, to_unit, GROW, FULL, RAMPED,
 )
 from .classify_oracle import accuracy, accuracy_bounds, classes  # noqa: F401
+from . import envelope  # noqa: F401  (float32 envelopes for the comparison protocol)

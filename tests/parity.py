@@ -1,98 +1,114 @@
 """Comparison protocol between the device results and the CPU oracle.
 
-Fitness values (float32 on the device, float64 in the oracle):
-  a tree is well-conditioned when the float64 oracle value m64 and the
-  float32 shadow value m32s are both finite and |m32s - m64| <= 0.1 * tol,
-  tol = max(1e-5 |m64|, 1e-6). Well-conditioned trees must satisfy
-  |m_gpu - m64| <= tol (the relative 1e-5 / absolute 1e-6 bar).
-  The rest are reported; for them the device value must agree with the
-  shadow (same non-finite class, or within 1e-3 relative) for all but a
-  small fraction, since float32 evaluation of an ill-conditioned tree has
-  no unique answer (branch flips of protected operators, cancellation).
+Fitness (float32 on the device, float64 in the oracle). For every valid tree
+the oracle gives the float64 value m64 and the envelope [lo, hi] of every
+float32 evaluation its arithmetic model allows (oracle/envelope.py), with a
+flag where a NaN is possible. The device value must lie inside the envelope
+(NaN only where a NaN is possible): every tree, no exceptions. Where the
+envelope lies within tol = max(1e-5 |m64|, 1e-6) of m64 (a "tight" tree), the
+containment is the relative 1e-5 / absolute 1e-6 bar itself. Elsewhere no
+float32 evaluation is determined to that bar, and the envelope is the bar.
+Invalid trees must give NaN.
 
-  The device's transcendental functions are a float32 library within a few
-  ulp of the correctly rounded results the shadow uses. So `shadows()` also
-  returns two shadows whose transcendental results move by random steps of
-  up to 2 ulp, and a tree is well-conditioned only if every shadow passes.
+Gradients: the same with the gradient envelopes and tol = 1e-3 |g64|
+(relative 1e-3) per component: constants' gradients and X gradients.
+
+The reports give the count of each class and the largest relative error of
+the device value against m64 over the tight trees.
 """
 
 import numpy as np
 
 import oracle as O
+from oracle import envelope as E
 
 REL = 1e-5
 ABS = 1e-6
-LIB_ULP = 2
-SEEDS = (1, 2)
+GRAD_REL = 1e-3
 
 
-def shadows(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None):
-    """[3][R]: the float32 shadow, then two with transcendental results perturbed by up to LIB_ULP ulp."""
-    out = [O.mse_shadow32(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows)]
-    for seed in SEEDS:
-        out.append(O.mse_shadow32(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows, ulp=LIB_ULP, seed=seed))
-    return np.stack(out)
+class FitnessRef:
+    """float64 fitness and float32 envelopes of a set of rows."""
+
+    def __init__(self, pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None):
+        self.m64 = O.mse(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows)
+        self.lo, self.hi, self.nan = E.fitness(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows)
 
 
-def classify(m64, m32s):
-    """m32s: one shadow [R] or shadows [S][R] (the first unperturbed)."""
-    m64 = np.asarray(m64, np.float64)
-    m32s = np.atleast_2d(np.asarray(m32s, np.float64))
+def inside(v, lo, hi, nan):
+    v = np.asarray(v, np.float64)
+    with np.errstate(invalid="ignore"):
+        return np.where(np.isnan(v), nan, (lo <= v) & (v <= hi))
+
+
+def compare_fitness(got, ref, label=""):
+    """Assert the protocol on device fitness values `got` (same rows as ref); return a report."""
+    got = np.asarray(got, np.float64)
+    m64 = ref.m64
+    valid = ~np.isnan(ref.lo) | ~np.isnan(ref.hi)
+    invalid = ~valid
+    bad_invalid = invalid & ~np.isnan(got)
+    assert not bad_invalid.any(), f"{label}: invalid trees without NaN fitness: {np.nonzero(bad_invalid)[0][:5]}"
+    ok = inside(got, ref.lo, ref.hi, ref.nan) | invalid
+    if not ok.all():
+        i = np.nonzero(~ok)[0][:5]
+        raise AssertionError(f"{label}: {int((~ok).sum())}/{len(got)} device fitness values outside the float32 "
+                             f"envelope; e.g. rows {i.tolist()} gpu {got[i].tolist()} envelope "
+                             f"{list(zip(ref.lo[i].tolist(), ref.hi[i].tolist()))} float64 {m64[i].tolist()}")
     tol = np.maximum(REL * np.abs(m64), ABS)
     with np.errstate(invalid="ignore"):
-        well = np.isfinite(m64) & np.all(np.isfinite(m32s) & (np.abs(m32s - m64) <= 0.1 * tol), axis=0)
-    return well, tol
-
-
-def compare_fitness(got, m64, m32s, max_ill_mismatch=0.05, label=""):
-    """Assert the protocol; return a small report dict."""
-    got = np.asarray(got, np.float64)
-    m64 = np.asarray(m64, np.float64)
-    well, tol = classify(m64, m32s)
-    m32s = np.atleast_2d(np.asarray(m32s, np.float64))[0]
-    with np.errstate(invalid="ignore"):
+        tight = valid & np.isfinite(m64) & ~ref.nan & (ref.lo >= m64 - tol) & (ref.hi <= m64 + tol)
         err = np.abs(got - m64)
-        bad = well & ~(err <= tol)
-    if bad.any():
-        i = np.nonzero(bad)[0][:5]
-        raise AssertionError(f"{label}: {int(bad.sum())}/{int(well.sum())} well-conditioned trees out of "
-                             f"tolerance; e.g. idx {i.tolist()} gpu {got[i].tolist()} oracle {m64[i].tolist()}")
-    ill = ~well
+        rel = err[tight] / np.maximum(np.abs(m64[tight]), ABS / REL)
+        width = (ref.hi - ref.lo) / np.abs(m64)
+    wide = valid & ~tight
+    return {"n": len(got), "tight": int(tight.sum()), "wide": int(wide.sum()), "invalid": int(invalid.sum()),
+            "nan_possible": int((valid & ref.nan).sum()),
+            "max_rel_err_tight": float(rel.max()) if rel.size else 0.0,
+            "median_rel_width_wide": float(np.median(width[wide])) if wide.any() else 0.0}
+
+
+class GradRef:
+    """float64 gradients and float32 envelopes of sum_t g_t fitness_t over a set of rows.
+    lanes_k: the fewest points per lane the device may use (more point tiles, so the widest
+    bound on the sums over points)."""
+
+    def __init__(self, pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, lanes_k=2):
+        self.m64, self.gv64, self.gx64 = O.grad(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows, g=g)
+        (self.gv_lo, self.gv_hi, self.gv_nan,
+         self.gx_lo, self.gx_hi, self.gx_nan) = E.grad(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows, g=g,
+                                                       lanes_k=lanes_k)
+        rows = list(range(pop_type.shape[0]) if rows is None else rows)
+        self.const = np.asarray(pop_type)[rows] == O.T_CONST
+
+
+def _grad_check(got, g64, lo, hi, nan, mask, label):
+    got = np.asarray(got, np.float64)
+    ok = inside(got, lo, hi, nan) | ~mask
+    if not ok.all():
+        idx = np.argwhere(~ok)[:5]
+        raise AssertionError(f"{label}: {int((~ok).sum())}/{int(mask.sum())} components outside the float32 "
+                             f"envelope; e.g. {[(tuple(int(x) for x in i), float(got[tuple(i)]), float(lo[tuple(i)]), float(hi[tuple(i)]), float(g64[tuple(i)])) for i in idx]}")
+    tol = GRAD_REL * np.abs(g64)
     with np.errstate(invalid="ignore"):
-        fin = np.isfinite(m32s)
-        ok = np.where(fin, np.abs(got - m32s) <= 1e-3 * np.abs(m32s) + 1e-6,
-                      ~np.isfinite(got) & (np.isnan(got) == np.isnan(m32s)))
-    ill_bad = ill & ~ok
-    frac = float(ill_bad.sum()) / max(1, len(got))
-    assert frac <= max_ill_mismatch, f"{label}: {int(ill_bad.sum())} ill-conditioned mismatches ({frac:.3%})"
-    rel = err[well] / np.maximum(np.abs(m64[well]), 1e-30)
-    return {"n": len(got), "well": int(well.sum()), "ill": int(ill.sum()), "ill_mismatch": int(ill_bad.sum()),
-            "max_rel_err_well": float(rel.max()) if rel.size else 0.0}
+        tight = mask & np.isfinite(g64) & ~nan & (lo >= g64 - tol) & (hi <= g64 + tol)
+        rel = np.abs(got - g64)[tight] / np.maximum(np.abs(g64[tight]), 1e-300)
+        width = (hi - lo) / np.abs(g64)
+    wide = mask & ~tight
+    return {"n": int(mask.sum()), "tight": int(tight.sum()), "wide": int(wide.sum()),
+            "nan_possible": int((mask & nan).sum()),
+            "max_rel_err_tight": float(rel.max()) if rel.size else 0.0,
+            "median_rel_width_wide": float(np.nanmedian(width[wide])) if wide.any() else 0.0}
 
 
-def grad_shadows(pop_type, pop_value, pop_size, X, Y, rows=None):
-    """Float32 shadows of the gradient sweep: [(grad_value, grad_X)] unperturbed, then perturbed as in shadows()."""
-    out = []
-    for ulp, seed in [(0, 0)] + [(LIB_ULP, sd) for sd in SEEDS]:
-        _, gv, gx = O.grad(pop_type, pop_value, pop_size, X, Y, rows=rows, shadow=True, ulp=ulp, seed=seed)
-        out.append((gv, gx))
-    return out
+def compare_grad_value(got, ref, label=""):
+    """Constant gradients [R][Lmax] against the envelopes; zero off the constants."""
+    got = np.asarray(got, np.float64)
+    assert (got[~ref.const] == 0).all(), f"{label}: non-zero gradient at a non-constant position"
+    return _grad_check(got, ref.gv64, ref.gv_lo, ref.gv_hi, ref.gv_nan, ref.const, label + " grad_value")
 
 
-def grad_close(g, ref, rel):
-    """|g - ref| <= rel * max(|ref|, 1e-3 * max|ref| of the row) + 1e-7, elementwise, per row."""
-    g = np.asarray(g, np.float64)
-    ref = np.asarray(ref, np.float64)
-    scale = np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref), axis=-1, keepdims=True))
-    with np.errstate(invalid="ignore"):
-        return np.abs(g - ref) <= rel * scale + 1e-7
-
-
-def well_grad(shadow_list, gv64, gx64, rel_v=1e-4, rel_x=2e-4):
-    """Components whose every float32 shadow agrees with float64 to a tenth of the tolerance."""
-    wv = np.ones(np.shape(gv64), bool)
-    wx = np.ones(np.shape(gx64), bool)
-    for gv, gx in shadow_list:
-        wv &= grad_close(gv, gv64, rel_v)
-        wx &= grad_close(gx, gx64, rel_x)
-    return wv, wx
+def compare_grad_x(got, ref, label=""):
+    """X gradients [V][D] against the envelopes."""
+    got = np.asarray(got, np.float64)
+    return _grad_check(got, ref.gx64, ref.gx_lo, ref.gx_hi, ref.gx_nan, np.ones(got.shape, bool), label + " grad_X")

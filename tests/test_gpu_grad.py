@@ -1,5 +1,6 @@
 """Device gradients (adjoint kernel through tgp_eval_mse_grad) against the CPU
-oracle's tape gradient and central finite differences; autograd and Adam."""
+oracle's tape gradient, its float32 envelopes and central finite
+differences; autograd and Adam with a gradient check at every step."""
 
 import numpy as np
 import pytest
@@ -8,8 +9,7 @@ import torch
 import oracle as O
 import paper_2501_17168_amd as tgp
 import synth
-from parity import shadows, classify, compare_fitness, grad_shadows, well_grad
-from parity import grad_close as _grad_close
+from parity import FitnessRef, GradRef, compare_fitness, compare_grad_value, compare_grad_x
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -21,118 +21,137 @@ def work(name="grad", **kw):
     if key not in _cache:
         w = synth.workload(name, **kw)
         Y = w.Y if w.Y is not None else w.targets_from(O.predict(*w.hidden, w.X, 1)[:, 0, :])
-        _cache[key] = (w, Y)
+        _cache[key] = (w, np.ascontiguousarray(Y, dtype=np.float32))
     return _cache[key]
 
 
-def dev_pop(w):
-    return tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (w.type, w.value, w.size)))
+def dev_pop(w, value=None):
+    v = w.value if value is None else value
+    return tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (w.type, v, w.size)))
 
 
-def grad_close(g, ref, rel=1e-3):
-    return _grad_close(g, ref, rel)
+_grefs = {}
 
 
-@pytest.mark.parametrize("name,P,D", [("grad", 400, 3100), ("hybrid", 300, 2000), ("plain", None, None)])
-def test_grad_matches_oracle(name, P, D):
-    w, Y = work(name, P=P, D=D)
+def grad_ref(name, w, Y, g=None):
+    key = (name, w.P, w.D, None if g is None else g.tobytes())
+    if key not in _grefs:
+        _grefs[key] = GradRef(w.type, w.value, w.size, w.X, Y, g=g)
+    return _grefs[key]
+
+
+# every workload shape that has single-output trees: the 11-op set (hybrid, grad), the paper's
+# set with tan (pagie), the 4-op set (plain) and a data-parallel shape (5 variables, D far above
+# one point tile, a ragged last tile)
+GRAD_CASES = [("grad", dict(P=300, D=3100)), ("hybrid", dict(P=250, D=2000)), ("plain", {}),
+              ("pagie", dict(P=250, D=2000)), ("dataparallel", dict(P=24, D=131_077))]
+
+
+@pytest.mark.parametrize("name,kw", GRAD_CASES)
+@pytest.mark.parametrize("k", [2, 4])
+def test_grad_matches_oracle(name, kw, k):
+    w, Y = work(name, **kw)
     pop = dev_pop(w)
     X = torch.from_numpy(w.X).to(DEV)
-    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
-    m64 = O.mse(w.type, w.value, w.size, w.X, Y)
-    m32 = shadows(w.type, w.value, w.size, w.X, Y)
-    well, _ = classify(m64, m32)
-    # only well-conditioned trees feed the X gradient: their upstream weight is 1, the others' 0
-    gw = np.where(well, 1.0, 0.0).astype(np.float32)
-    mse, gv, gx = tgp.eval_mse_grad(pop, X, Yd, grad_mse=torch.from_numpy(gw).to(DEV))
+    Yd = torch.from_numpy(Y).to(DEV)
+    mse, gv, gx = tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, points_per_lane=k))
     torch.cuda.synchronize()
-    compare_fitness(mse.cpu().numpy(), m64, m32, label=f"{name} fitness from the gradient call")
-    rows = np.nonzero(well)[0]
-    _, gv64, gx64 = O.grad(w.type, w.value, w.size, w.X, Y, rows=rows)
-    gvd = gv.cpu().numpy()[rows]
-    const = w.type[rows] == 1
-    # a component is well-conditioned when every float32 shadow of the sweep
-    # agrees with float64 to a tenth of the tolerance; near-singular
-    # quotients under bounded functions make a few components depend on
-    # float32 rounding even in trees whose fitness does not
-    wv, wellx = well_grad(grad_shadows(w.type, w.value, w.size, w.X, Y, rows=rows), gv64, gx64)
-    wellg = wv & const
-    ok = grad_close(gvd, gv64) | ~wellg
-    frac_bad = 1.0 - ok[wellg].mean()
-    print(f"{name}: {wellg.sum()} well-conditioned constant gradients, {(const & ~wellg).sum()} ill-conditioned; "
-          f"{frac_bad:.4%} outside 1e-3")
-    assert wellg.sum() >= 0.8 * const.sum()
-    assert frac_bad <= 0.005, (name, frac_bad, np.argwhere(~ok)[:5])
-    assert (gvd[~const] == 0).all()
-    gxd = gx.cpu().numpy()
-    okx = grad_close(gxd, gx64, rel=2e-3) | ~wellx
-    assert wellx.mean() >= 0.9
-    assert okx.mean() >= 0.995, (name, 1 - okx.mean())
+    ref = grad_ref(name, w, Y)
+    rep_f = compare_fitness(mse.cpu().numpy(), FitnessRef(w.type, w.value, w.size, w.X, Y), label=f"{name} fitness")
+    rep_v = compare_grad_value(gv.cpu().numpy(), ref, label=name)
+    rep_x = compare_grad_x(gx.cpu().numpy(), ref, label=name)
+    print(f"{name} K={k}: fitness {rep_f}\n  grad_value {rep_v}\n  grad_X {rep_x}", flush=True)
+    # the envelopes are narrow enough to mean something on most components
+    assert rep_v["tight"] >= 0.25 * rep_v["n"], rep_v
+    assert rep_x["tight"] >= 0.25 * rep_x["n"], rep_x
 
 
 def test_grad_vs_finite_differences():
-    w, Y = work("grad", P=400, D=3100)
+    """Device constant gradients against central differences of the float64 fitness (h = 1e-4)
+    on sampled constants whose float32 envelope is within 1e-3 of the float64 gradient; the
+    difference quotient's own error is estimated from h and h/4 and allowed for."""
+    w, Y = work("grad", P=300, D=3100)
     pop = dev_pop(w)
     X = torch.from_numpy(w.X).to(DEV)
-    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
     _, gv, _ = tgp.eval_mse_grad(pop, X, Yd)
     gv = gv.cpu().numpy()
-    m64 = O.mse(w.type, w.value, w.size, w.X, Y)
-    m32 = shadows(w.type, w.value, w.size, w.X, Y)
-    well, _ = classify(m64, m32)
+    ref = grad_ref("grad", w, Y)
+    tol = 1e-3 * np.abs(ref.gv64)
+    with np.errstate(invalid="ignore"):
+        tight = ref.const & ~ref.gv_nan & (ref.gv_lo >= ref.gv64 - tol) & (ref.gv_hi <= ref.gv64 + tol)
     rng = np.random.default_rng(0)
-    cand = [p for p in np.nonzero(well & ((w.type == 1).sum(1) > 0) & (m64 < 1e4))[0]]
-    checked = agree = 0
-    for p in rng.choice(cand, size=min(100, len(cand)), replace=False):
-        i = int(rng.choice(np.nonzero(w.type[p] == 1)[0]))
-        _, g64, gx64 = O.grad(w.type, w.value, w.size, w.X, Y, rows=[p])
-        wv, _ = well_grad(grad_shadows(w.type, w.value, w.size, w.X, Y, rows=[p]), g64, gx64)
-        if not wv[0, i]:
-            continue   # float32-sensitive component
+    cand = np.argwhere(tight & (np.abs(ref.gv64) > 1e-6))
+    checked = 0
+    for p, i in cand[rng.choice(len(cand), size=min(100, len(cand)), replace=False)]:
+        if not (ref.m64[p] < 1e4):
+            continue                    # the difference quotient cancels badly on huge fitness values
         f1 = O.fd_grad_const(w.type, w.value, w.size, w.X, Y, p, i, h=1e-4)
         f2 = O.fd_grad_const(w.type, w.value, w.size, w.X, Y, p, i, h=2.5e-5)
-        if abs(f1 - f2) > 1e-3 * max(abs(f2), 1e-6):
-            continue   # kink-adjacent
+        fd_err = abs(f1 - f2)           # the quotient at h/4 is within about this of the derivative
+        assert abs(gv[p, i] - f2) <= 1e-3 * abs(f2) + 2.0 * fd_err + 1e-9, (p, i, gv[p, i], f1, f2)
         checked += 1
-        agree += abs(gv[p, i] - f2) <= 1e-3 * max(abs(f2), 1e-4) + 1e-6
     assert checked >= 50
-    assert agree >= 0.98 * checked, (agree, checked)
 
 
-def test_autograd_and_adam():
+def test_autograd_matches_direct_call():
+    """TreeMSE backward with upstream weights equals the direct call's gradients up to the order
+    of the float32 sums: both inside the envelopes of the weighted gradients."""
     w, Y = work("grad", P=200, D=2000)
     value = torch.from_numpy(w.value.copy()).to(DEV).requires_grad_(True)
     type_ = torch.from_numpy(w.type).to(DEV)
     size = torch.from_numpy(w.size).to(DEV)
     X = torch.from_numpy(w.X).to(DEV).requires_grad_(True)
-    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
     mse = tgp.TreeMSE.apply(value, type_, size, X, Yd)
-    w_t = torch.linspace(0.5, 1.5, w.P, device=DEV)
-    (mse * w_t).sum().backward()
+    wt = np.linspace(0.5, 1.5, w.P).astype(np.float32)
+    (mse * torch.from_numpy(wt).to(DEV)).sum().backward()
     pop = tgp.Population(type_, value.detach(), size)
-    _, gv, gx = tgp.eval_mse_grad(pop, X.detach(), Yd, grad_mse=w_t.contiguous())
-    # same sums, but float atomics add the per-wave partials in run-dependent
-    # order: equal zero pattern, values equal to rounding (components with
-    # heavy cancellation may differ more, so a small fraction is allowed)
-    a = torch.nan_to_num(value.grad).cpu().numpy()
-    b = torch.nan_to_num(gv).cpu().numpy()
-    np.testing.assert_array_equal(a == 0, b == 0)
-    assert np.isclose(a, b, rtol=1e-5, atol=0).mean() > 0.999
-    assert np.isclose(X.grad.cpu().numpy(), gx.cpu().numpy(), rtol=1e-5, atol=1e-7).mean() > 0.999
-    # 10 Adam steps on the constants: padding and non-constant fields never move
-    v2 = torch.from_numpy(w.value.copy()).to(DEV).requires_grad_(True)
-    opt = torch.optim.Adam([v2], lr=1e-2)
-    m0 = tgp.TreeMSE.apply(v2, type_, size, X.detach(), Yd).detach().clone()
-    for _ in range(10):
+    _, gv, gx = tgp.eval_mse_grad(pop, X.detach(), Yd, grad_mse=torch.from_numpy(wt).to(DEV))
+    ref = grad_ref("grad-weighted", w, Y, g=wt)
+    for label, a, b in (("autograd", value.grad, X.grad), ("direct", gv, gx)):
+        compare_grad_value(a.cpu().numpy(), ref, label)
+        compare_grad_x(b.cpu().numpy(), ref, label)
+
+
+def _adam_with_checks(w, Y, rows_per_step, steps=10, lr=1e-2, value_rows=None):
+    """Adam (torch.optim.Adam, lr 1e-2) on the constants through TreeMSE. Before every step the
+    device gradient of the checked rows is compared with the oracle's envelopes at the device's
+    current constants. Returns the first and last fitness."""
+    value = torch.from_numpy(w.value.copy()).to(DEV).requires_grad_(True)
+    type_ = torch.from_numpy(w.type).to(DEV)
+    size = torch.from_numpy(w.size).to(DEV)
+    X = torch.from_numpy(w.X).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
+    opt = torch.optim.Adam([value], lr=lr)
+    m_first = None
+    for step in range(steps):
         opt.zero_grad()
-        tgp.TreeMSE.apply(v2, type_, size, X.detach(), Yd).sum().backward()
+        mse = tgp.TreeMSE.apply(value, type_, size, X, Yd)
+        mse.sum().backward()
+        torch.cuda.synchronize()
+        if m_first is None:
+            m_first = mse.detach().cpu().numpy()
+        rows = rows_per_step(step)
+        cur = value.detach().cpu().numpy()
+        ref = GradRef(w.type, cur, w.size, w.X, Y, rows=rows)
+        compare_fitness(mse.detach().cpu().numpy()[rows], FitnessRef(w.type, cur, w.size, w.X, Y, rows=rows),
+                        label=f"Adam step {step} fitness")
+        rep = compare_grad_value(value.grad.cpu().numpy()[rows], ref, label=f"Adam step {step}")
+        print(f"step {step}: {len(rows)} trees, grad_value {rep}", flush=True)
         opt.step()
-    vv = v2.detach().cpu().numpy()
+    m_last = tgp.TreeMSE.apply(value.detach(), type_, size, X, Yd).cpu().numpy()
+    return value.detach().cpu().numpy(), m_first, m_last
+
+
+def test_adam_steps_with_gradient_checks():
+    w, Y = work("grad", P=200, D=2000)
+    vv, m0, m1 = _adam_with_checks(w, Y, lambda step: list(range(w.P)))
+    # padding and non-constant fields never move; NaN stays NaN
     fixed = w.type != 1
     np.testing.assert_array_equal(np.isnan(vv), np.isnan(w.value))
-    assert np.array_equal(vv[fixed & ~np.isnan(w.value)], w.value[fixed & ~np.isnan(w.value)])
-    m1 = tgp.TreeMSE.apply(v2.detach(), type_, size, X.detach(), Yd).cpu().numpy()
-    m0 = m0.cpu().numpy()
+    keep = fixed & ~np.isnan(w.value)
+    assert np.array_equal(vv[keep], w.value[keep])
     fin = np.isfinite(m0) & np.isfinite(m1) & ((w.type == 1).sum(1) > 0)
     assert (m1[fin] <= m0[fin] * (1 + 1e-6)).mean() > 0.8
 
@@ -141,7 +160,7 @@ def test_graph_replay_matches_eager():
     w, Y = work("hybrid", P=600, D=2000)
     pop = dev_pop(w)
     X = torch.from_numpy(w.X).to(DEV)
-    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
     ws = tgp.Workspace(DEV)
     out = torch.empty(w.P, device=DEV)
     c = tgp.cfg(mode=3, points_per_lane=4, trees_per_unit=4)
@@ -171,21 +190,22 @@ def test_graph_replay_matches_eager():
                                  dict(points_per_lane=2, block_waves=4, trees_per_unit=16), "tuned"])
 def test_grad_launch_shapes_agree(cfg):
     """Every workgroup shape and trees-per-unit choice of the gradient call, and the autotuned one
-    (tgp_autotune with want_grad, then a call without a configuration), give the default call's
-    fitness and gradients up to the order of the atomic sums."""
-    w, Y = work("grad", P=400, D=3100)
+    (tgp_autotune with want_grad, then a call without a configuration): fitness and gradients
+    inside the oracle's envelopes."""
+    w, Y = work("grad", P=300, D=3100)
     pop = dev_pop(w)
     X = torch.from_numpy(w.X).to(DEV)
-    Yd = torch.from_numpy(np.ascontiguousarray(Y)).to(DEV)
-    ref = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd)]
+    Yd = torch.from_numpy(Y).to(DEV)
     if cfg == "tuned":
         tuned = tgp.autotune(pop, X, Yd, want_grad=True)
         print(f"tuned gradient launch: {tuned}", flush=True)
         assert tuned["mode"] == 2 and tuned["points_per_lane"] in (2, 4)
-        got = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd)]
+        got = tgp.eval_mse_grad(pop, X, Yd)
     else:
-        got = [t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, **cfg))]
+        got = tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, **cfg))
     torch.cuda.synchronize()
-    for name, a, b in zip(("mse", "grad_value", "grad_X"), got, ref):
-        scale = np.nanmax(np.abs(b))
-        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6 * scale, equal_nan=True, err_msg=name)
+    mse, gv, gx = (t.cpu().numpy() for t in got)
+    ref = grad_ref("grad", w, Y)
+    compare_fitness(mse, FitnessRef(w.type, w.value, w.size, w.X, Y), label=f"{cfg} fitness")
+    compare_grad_value(gv, ref, label=str(cfg))
+    compare_grad_x(gx, ref, label=str(cfg))

@@ -103,6 +103,85 @@ def test_partials_match_finite_differences(op):
         np.testing.assert_allclose(da, fa, rtol=1e-6, atol=1e-7)
 
 
+# The conventions at the operators' kinks (the operator table's readings): the value of
+# protected division switches to 1 only strictly below tau, the clamped exp keeps its slope
+# at exactly +-20, protected log has slope 0 at a = 0 (either sign), and max / min give the
+# whole slope to the first operand at a tie (and to the operand returned when the other is NaN).
+# Expected values are written out by hand from those readings.
+_TAU32 = float(np.float32(1e-6))
+_BELOW_TAU = float(np.nextafter(np.float32(1e-6), np.float32(0)))
+_ABOVE_20 = float(np.nextafter(np.float32(20.0), np.float32(np.inf)))
+KINK_PARTIALS = [
+    # op, a, b, d/da, d/db
+    (9, 1.5, 1.5, 1.0, 0.0), (9, -2.0, -2.0, 1.0, 0.0), (9, 0.0, -0.0, 1.0, 0.0),
+    (9, 1.0, 2.0, 0.0, 1.0), (9, 2.0, 1.0, 1.0, 0.0),
+    (9, np.nan, 2.0, 0.0, 1.0), (9, 2.0, np.nan, 1.0, 0.0),
+    (10, 1.5, 1.5, 1.0, 0.0), (10, -2.0, -2.0, 1.0, 0.0), (10, -0.0, 0.0, 1.0, 0.0),
+    (10, 1.0, 2.0, 1.0, 0.0), (10, 2.0, 1.0, 0.0, 1.0),
+    (10, np.nan, 2.0, 0.0, 1.0), (10, 2.0, np.nan, 1.0, 0.0),
+    (3, 3.0, _TAU32, 1.0 / _TAU32, -3.0 / (_TAU32 * _TAU32)),
+    (3, 3.0, -_TAU32, -1.0 / _TAU32, -3.0 / (_TAU32 * _TAU32)),
+    (3, 3.0, _BELOW_TAU, 0.0, 0.0), (3, 3.0, -_BELOW_TAU, 0.0, 0.0),
+    (3, 3.0, 0.0, 0.0, 0.0), (3, 3.0, -0.0, 0.0, 0.0),
+    (8, 0.0, None, 0.0, None), (8, -0.0, None, 0.0, None),
+    (8, 2.0, None, 1.0 / (2.0 + _TAU32), None), (8, -2.0, None, -1.0 / (2.0 + _TAU32), None),
+    (7, 20.0, None, math.exp(20.0), None), (7, -20.0, None, math.exp(-20.0), None),
+    (7, _ABOVE_20, None, 0.0, None), (7, -_ABOVE_20, None, 0.0, None),
+    (7, 25.0, None, 0.0, None), (7, -25.0, None, 0.0, None),
+]
+KINK_VALUES = [
+    # op, a, b, f(a, b)
+    (3, 3.0, _TAU32, 3.0 / _TAU32), (3, 3.0, -_TAU32, -3.0 / _TAU32),
+    (3, 3.0, _BELOW_TAU, 1.0), (3, 3.0, -_BELOW_TAU, 1.0), (3, -7.0, 0.0, 1.0),
+    (7, 20.0, None, math.exp(20.0)), (7, _ABOVE_20, None, math.exp(20.0)), (7, -25.0, None, math.exp(-20.0)),
+    (8, 0.0, None, math.log(_TAU32)), (8, -0.0, None, math.log(_TAU32)),
+    (9, np.nan, 2.0, 2.0), (10, 2.0, np.nan, 2.0), (9, np.nan, np.nan, np.nan),
+]
+
+
+@pytest.mark.parametrize("op,a,b,da,db", KINK_PARTIALS)
+def test_partials_at_kinks(op, a, b, da, db):
+    A = np.array([a])
+    if b is None:
+        got, _ = O.op_partials(op, A)
+        assert got[0] == da
+    else:
+        ga, gb = O.op_partials(op, A, np.array([b]))
+        assert ga[0] == da and gb[0] == db
+
+
+@pytest.mark.parametrize("op,a,b,f", KINK_VALUES)
+def test_values_at_kinks(op, a, b, f):
+    got = O.apply_op(op, np.array([a])) if b is None else O.apply_op(op, np.array([a]), np.array([b]))
+    if np.isnan(f):
+        assert np.isnan(got[0])
+    else:
+        assert got[0] == f
+
+
+def test_tree_gradient_at_ties_goes_to_first_operand():
+    """MAX(c, x0) and MIN(x0, c) with x0 equal to c at some points: at those points the whole
+    slope goes to the first operand, written out here as the gradient of the mean square."""
+    c = 1.5
+    X = np.array([[1.5, 0.5, 1.5, 3.0, 1.5]])
+    Y = np.array([[0.25, -1.0, 2.0, 0.0, 1.0]])
+    D = X.shape[1]
+    for op, first_is_const in ((9, True), (10, False)):
+        nodes = [(2, op, 3), (1, c, 1), (0, 0, 1)] if first_is_const else [(2, op, 3), (0, 0, 1), (1, c, 1)]
+        t, v, s = _rows(nodes, 8)
+        m, gv, gX = O.grad(t[None], v[None], s[None], X, Y)
+        x = X[0]
+        out = np.maximum(c, x) if op == 9 else np.minimum(x, c)
+        r = 2.0 / D * (out - Y[0])
+        if op == 9:
+            to_c = x <= c          # c is first: ties go to c
+        else:
+            to_c = x > c           # x0 is first: ties go to x0
+        ci = 1 if first_is_const else 2
+        assert gv[0, ci] == pytest.approx(float(np.sum(np.where(to_c, r, 0.0))), rel=1e-15, abs=1e-300)
+        np.testing.assert_allclose(gX[0], np.where(to_c, 0.0, r), rtol=1e-15, atol=0)
+
+
 def test_shadow32_matches_float32_arithmetic():
     r = np.random.default_rng(7)
     a = r.uniform(-10, 10, 1000).astype(np.float32)
