@@ -7,16 +7,24 @@ data point and reduce the squared errors (evaluation kernel), write one
 fitness per tree (finalize). The metric is GPops/s = sum of tree lengths x
 data points / time (Langdon's measure as used in the paper's §V-C, with one
 generation per step). Inputs are seeded synthetic data of the workload's
-shape, already in device memory when the timed region starts.
+shape, already in device memory when the timed region starts. The default
+workload is the largest: 200,000 trees of lengths 3..1024 (10% with three
+Modi outputs) on 4,096 points, one persistent launch.
 
 Prints one JSON line. Extra objects:
-  roofline      the evaluation kernel against the vector-ALU issue peak;
+  roofline      the evaluation kernel against the vector-ALU issue peak, with
+                algorithmic operations from a fixed operator cost table;
   cpu_baseline  the CPU oracle timed on the host (a baseline, not a target);
   forms         the same workload through the plain forward kernel (one tree
-                per workgroup, fixed shape), the batched persistent queue
-                replayed as a captured hipGraph, and forward + adjoint
-                (fitness, d/d constants and d/dX), each in GPops/s and as a
+                per workgroup, fixed shape) and the batched persistent queue
+                replayed as a captured hipGraph, each in GPops/s and as a
                 ratio to the plain forward kernel;
+  differentiation  the differentiation workload (50,000 trees, 65,536
+                points): forward + adjoint (fitness, d/d constants, d/dX)
+                against the plain forward kernel, and the adjoint kernel's
+                roofline;
+  data_parallel the data-parallel workload (1,000 trees, 10^6 points): step
+                throughput and the evaluation kernel's HBM bytes per second;
   exchange      the subtree-exchange kernel (§III-B) producing the next
                 population by one-point crossover, in children per second,
                 against the HBM bandwidth peak;
@@ -41,7 +49,19 @@ METRIC = "GPops/s (tree nodes × points / s), fwd MSE and fwd+adjoint vs plain f
 # MI355X: 256 CUs x 4 SIMD x 16 lanes, one fp32 lane-op per lane per clock (non-packed), 2.4 GHz
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 OP_NAMES = ("add", "sub", "mul", "div", "sin", "cos", "tanh", "exp", "log", "max", "min", "tan")
+# Fixed operator cost table, in vector-ALU issue slots per application and lane: the cost of
+# each operator in compiled (not interpreted) gfx950 code, measured once on MI355X with the
+# per-operator loop of tgp_op_cost (spread random inputs, so lanes take the library's
+# data-dependent branches) and frozen here, so that the algorithmic operation count of a
+# workload does not depend on the build being measured. max and min are one instruction each.
+OP_COST = (1.0, 1.0, 1.0, 14.1, 16.9, 15.2, 20.3, 15.6, 12.0, 1.0, 1.0, 22.5)
+# Cost of an operator's partial derivatives in the adjoint, same units: div 1/b (a division) and
+# -a/b^2 (two products) and the protection select; sin -> cos; cos -> sin; tanh 1 - t^2 after t;
+# exp its value and the clamp test; log sign(a) / (|a| + eps) (a division, an add, the a = 0
+# select); max / min one compare; tan 1 + t^2 after t; add, sub, mul need no arithmetic.
+PARTIAL_COST = (0.0, 0.0, 0.0, 17.1, 15.2, 16.9, 22.3, 16.6, 16.1, 1.0, 1.0, 24.5)
 EVAL_SOURCES = ("eval_impl.h", "interp.h", "tgp_isa.h", "tgp_kernels.h")
+ADJ_SOURCES = ("adjoint_impl.h", "interp.h", "tgp_isa.h", "tgp_kernels.h")
 XCHG_SOURCES = ("exchange.hip", "tgp_exchange.h")
 GEN_SOURCES = ("generate.hip", "tgp_generate.h")
 PEAK_HBM_GBS = 8000.0
@@ -53,17 +73,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="hybrid", choices=["plain", "hybrid", "dataparallel", "batched", "grad"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["plain", "hybrid", "dataparallel", "batched", "grad", "hybrid-arith", "batched-arith"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--save-cfg", default=None, help="write the chosen launch configuration (JSON) here")
     ap.add_argument("--load-cfg", default=None, help="use this launch configuration (JSON file) instead of tuning")
     ap.add_argument("--cfg", default=None, help="use this launch configuration (JSON text) instead of tuning")
-    ap.add_argument("--no-roofline", action="store_true", help="skip the operator-cost measurement (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the plain-forward / batched-persistent graph / forward+adjoint comparison")
     ap.add_argument("--form-steps", type=int, default=10, help="timed steps of each compared form")
+    ap.add_argument("--adj-cfg", default=None,
+                    help="launch configuration (JSON text) of the gradient call instead of tuning it")
+    ap.add_argument("--no-differentiation", action="store_true",
+                    help="skip the forward+adjoint measurement on the differentiation workload")
+    ap.add_argument("--no-data-parallel", action="store_true",
+                    help="skip the measurement on the data-parallel workload")
+    ap.add_argument("--op-cost-live", action="store_true",
+                    help="also measure the operator costs on this GPU (reported beside the fixed table)")
     ap.add_argument("--no-exchange", action="store_true", help="skip the subtree-exchange measurement")
     ap.add_argument("--exchange-steps", type=int, default=20)
     ap.add_argument("--no-generation", action="store_true", help="skip the tree-generation measurement")
@@ -99,10 +127,46 @@ def stored_traffic(workload, src_hash, kernel="eval"):
     return float(m_bytes.group(1))
 
 
-def op_costs(tgp):
-    """Cost of each operator in vector-ALU issue slots, measured live on spread random inputs."""
+def op_costs_live():
+    """Cost of each operator in vector-ALU issue slots, measured on this GPU (reported only)."""
     from paper_2501_17168_amd import _lib
     return [max(1.0, _lib.op_cost(o)) for o in range(len(OP_NAMES))]
+
+
+def op_counts(w):
+    """Function nodes of the workload's trees, per op id."""
+    import numpy as np
+    fn = w.type >= 2
+    return np.bincount(w.value[fn].astype(np.int64), minlength=len(OP_NAMES))
+
+
+def fwd_ops_per_point(w):
+    """Algorithmic forward operations per data point: every function node at its cost, plus the
+    residual and the squared accumulate of every output of every tree. Leaves cost nothing."""
+    import numpy as np
+    return float(np.dot(op_counts(w), OP_COST)) + 2.0 * w.P * w.n_out
+
+
+def adj_ops_per_point(w):
+    """Algorithmic forward + adjoint operations per data point: the forward operations; every
+    function node's partial derivatives; one product per child edge (the child's adjoint) and one
+    add per leaf (the gradient accumulation); two products per tree for the output adjoint.
+    Recomputation is not counted."""
+    import numpy as np
+    lengths = w.lengths()
+    edges = float(lengths.sum() - w.P)
+    leaves = float(np.count_nonzero((w.type == 0) | (w.type == 1)))
+    return fwd_ops_per_point(w) + float(np.dot(op_counts(w), PARTIAL_COST)) + edges + leaves + 2.0 * w.P
+
+
+def alu_roofline(ops_per_launch, kernel_ms, node_evals, kernel, src_hash, traffic):
+    achieved = ops_per_launch / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Top/s",
+            "frac": achieved / PEAK_LANE_OPS, "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms,
+            "algo_ops_per_launch": ops_per_launch,
+            "node_evals_per_s": node_evals / (kernel_ms * 1e-3),
+            "node_evals_frac": node_evals / (kernel_ms * 1e-3) / PEAK_LANE_OPS,
+            "op_cost": dict(zip(OP_NAMES, OP_COST)), "source_hash": src_hash}
 
 
 def timed_ms(torch, fn, steps, warmup=2):
@@ -165,8 +229,41 @@ def exchange_bench(tgp, torch, w, workload, steps, warmup=3):
             "full_write": {"ms": full_ms, "trees/s": B / (full_ms * 1e-3),
                            "roofline": roof(full_bytes, full_ms, "full")}}
 
+def device_workload(tgp, torch, w):
+    """The workload's population, X and Y in device memory. Targets of hidden trees are the
+    library's own predictions of those trees plus the workload's noise."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    pop = tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (w.type, w.value, w.size)))
+    X = torch.from_numpy(w.X).to(dev)
+    if w.Y is not None:
+        Y = torch.from_numpy(w.Y).to(dev)
+    else:
+        hidden = tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in w.hidden))
+        # each hidden tree is a plain (single-output) tree: its root value is target row o
+        _, hp = tgp.eval_multi_output(hidden, X, None, n_out=1, want_pred=True)
+        Y = (hp[:, 0, :] + torch.from_numpy(w.noise).to(dev)).contiguous()
+    torch.cuda.synchronize()
+    return pop, X, Y
+
+
+def profiled_ms(torch, fn, steps, warmup=2):
+    """Mean step time (HIP events on the current stream) and mean evaluation- or adjoint-kernel
+    time per launch (HIP events the library records around that launch, on the same stream)."""
+    from paper_2501_17168_amd import _lib
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    _lib.profile(True)
+    _lib.profile_read()
+    ms = timed_ms(torch, fn, steps, warmup=0)
+    k_total, launches = _lib.profile_read()
+    _lib.profile(False)
+    return ms, k_total / max(launches, 1)
+
+
 def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
-    """Plain forward vs batched persistent (hipGraph replay) vs forward + adjoint on one workload."""
+    """Plain forward vs batched persistent (hipGraph replay) on one workload."""
     res = {}
     plain = tgp.cfg(mode=1, points_per_lane=4, block_waves=4)
     ws = tgp.Workspace(X.device)
@@ -204,16 +301,72 @@ def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
     del g
 
     if w.n_out == 1:
-        # the gradient call's own launch shape, tuned like the forward's (later calls use it)
         adj_cfg = tgp.autotune(pop, X, Y, want_grad=True, ws=ws)
-
-        def fwd_adj():
-            tgp.eval_mse_grad(pop, X, Y, ws=ws)
-
-        ms_adj = timed_ms(torch, fwd_adj, steps)
+        ms_adj = timed_ms(torch, lambda: tgp.eval_mse_grad(pop, X, Y, ws=ws), steps)
         res["fwd_adjoint"] = {"outputs": "fitness, d/d constants, d/dX", "cfg": adj_cfg, "ms": ms_adj,
                               "GPops/s": gpops_per_step / (ms_adj * 1e-3), "vs_plain_fwd": ms_plain / ms_adj}
     return res
+
+
+def differentiation_bench(tgp, torch, steps, adj_cfg=None):
+    """Forward + adjoint on the differentiation workload (50,000 trees, <= 32 constants each,
+    8 variables, 65,536 points): fitness, d(sum of fitness)/d constants and d/dX in one call at
+    the gradient autotuner's launch shape, against the plain forward kernel (tree-major, 4 points
+    per lane, 4 waves per workgroup) and the autotuned forward on the same trees. The adjoint
+    kernel's roofline counts forward operations, partial derivatives and the sweep's products
+    and accumulations per point (no recomputation)."""
+    import synth
+    w = synth.workload("grad")
+    pop, X, Y = device_workload(tgp, torch, w)
+    ws = tgp.Workspace(X.device)
+    node_evals = float(w.lengths().sum()) * w.D
+    plain = tgp.cfg(mode=1, points_per_lane=4, block_waves=4)
+    ms_plain = timed_ms(torch, lambda: tgp.eval_mse(pop, X, Y, config=plain, ws=ws), steps)
+    fwd_cfg = tgp.autotune(pop, X, Y, ws=ws)
+    ms_fwd, fwd_kernel_ms = profiled_ms(torch, lambda: tgp.eval_mse(pop, X, Y, ws=ws), steps)
+    if adj_cfg is None:
+        adj_cfg = tgp.autotune(pop, X, Y, want_grad=True, ws=ws)
+    ac = tgp.cfg(adj_cfg)
+    ms_adj, adj_kernel_ms = profiled_ms(torch, lambda: tgp.eval_mse_grad(pop, X, Y, config=ac, ws=ws), steps)
+    roof = alu_roofline(adj_ops_per_point(w) * w.D, adj_kernel_ms, node_evals, "adjoint_kernel",
+                        eval_source_hash(ADJ_SOURCES), stored_traffic("grad", eval_source_hash(ADJ_SOURCES),
+                                                                      kernel="adjoint"))
+    roof["partial_cost"] = dict(zip(OP_NAMES, PARTIAL_COST))
+    return {"workload": f"grad: {w.desc}", "P": w.P, "D": w.D, "sum_len": int(w.lengths().sum()),
+            "plain_fwd": {"cfg": "tree-major, 4 points/lane, 4 waves/workgroup", "ms": ms_plain,
+                          "GPops/s": node_evals / (ms_plain * 1e-3)},
+            "tuned_fwd": {"cfg": fwd_cfg, "ms": ms_fwd, "GPops/s": node_evals / (ms_fwd * 1e-3),
+                          "eval_kernel_ms": fwd_kernel_ms},
+            "fwd_adjoint": {"outputs": "fitness, d/d constants, d/dX", "cfg": adj_cfg, "ms": ms_adj,
+                            "GPops/s": node_evals / (ms_adj * 1e-3), "vs_plain_fwd": ms_plain / ms_adj,
+                            "vs_tuned_fwd": ms_fwd / ms_adj, "adjoint_kernel_ms": adj_kernel_ms},
+            "roofline": roof}
+
+
+def data_parallel_bench(tgp, torch, steps):
+    """The data-parallel workload (1,000 trees, 5 variables, 10^6 points): autotuned step
+    throughput, the evaluation kernel against the vector-ALU peak, and its HBM bytes per second:
+    algorithmic (X and Y read once, the encoding, one fitness per tree) and, when the committed
+    counter summary matches the kernel source, measured."""
+    import synth
+    w = synth.workload("dataparallel")
+    pop, X, Y = device_workload(tgp, torch, w)
+    ws = tgp.Workspace(X.device)
+    sum_len = int(w.lengths().sum())
+    node_evals = float(sum_len) * w.D
+    cfg = tgp.autotune(pop, X, Y, ws=ws)
+    ms, kernel_ms = profiled_ms(torch, lambda: tgp.eval_mse(pop, X, Y, ws=ws), steps)
+    src = eval_source_hash()
+    traffic = stored_traffic("dataparallel", src)
+    algo_bytes = 4.0 * w.D * (w.V + w.n_out) + 12.0 * sum_len + 4.0 * w.P
+    hbm = {"bound": "hbm", "achieved": algo_bytes / (kernel_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": algo_bytes / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": traffic,
+           "traffic_GBs": None if traffic is None else traffic / (kernel_ms * 1e-3) / 1e9,
+           "algo_bytes_per_launch": algo_bytes, "kernel": "eval_kernel", "kernel_ms": kernel_ms}
+    return {"workload": f"dataparallel: {w.desc}", "P": w.P, "D": w.D, "sum_len": sum_len, "schedule": cfg,
+            "ms": ms, "GPops/s": node_evals / (ms * 1e-3),
+            "roofline": alu_roofline(fwd_ops_per_point(w) * w.D, kernel_ms, node_evals, "eval_kernel", src, traffic),
+            "hbm": hbm}
 
 
 _CPU = {}  # workload and targets for the oracle pool (inherited by forked workers)
@@ -424,16 +577,7 @@ def main():
     w = synth.workload(args.workload)
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, args.cpu_seconds)
     dev = torch.device("cuda:0")
-    pop = tgp.Population(*(torch.from_numpy(a).to(dev) for a in (w.type, w.value, w.size)))
-    X = torch.from_numpy(w.X).to(dev)
-    if w.Y is not None:
-        Y = torch.from_numpy(w.Y).to(dev)
-    else:
-        # targets: the hidden trees' predictions (computed by the library itself) plus noise
-        hidden = tgp.Population(*(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in w.hidden))
-        _, hp = tgp.eval_multi_output(hidden, X, None, n_out=1, want_pred=True)
-        Y = (hp[:, 0, :] + torch.from_numpy(w.noise).to(dev)).contiguous()
-    torch.cuda.synchronize()
+    pop, X, Y = device_workload(tgp, torch, w)
 
     lengths = w.lengths()
     sum_len = int(lengths.sum())
@@ -478,6 +622,7 @@ def main():
     _lib.profile(False)
     ms_step = ms / args.steps
     value = gpops_per_step * args.steps / (ms * 1e-3)
+    print(f"{args.workload}: {ms_step:.3f} ms per step, {value:.3e} GPops/s", file=sys.stderr, flush=True)
 
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -487,39 +632,36 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ---- roofline of the evaluation kernel (fixed operator cost table) ----
+    eval_ms = eval_ms_total / max(launches, 1)
+    src_hash = eval_source_hash()
+    roofline = alu_roofline(fwd_ops_per_point(w) * w.D, eval_ms, gpops_per_step, "eval_kernel", src_hash,
+                            stored_traffic(args.workload, src_hash))
+    if args.op_cost_live:
+        roofline["op_cost_live"] = dict(zip(OP_NAMES, (round(c, 2) for c in op_costs_live())))
+
     forms = None if args.no_forms else compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, args.form_steps, cfg)
+    if forms:
+        print(f"forms: {json.dumps(forms)}", file=sys.stderr, flush=True)
+    diff = None if args.no_differentiation else differentiation_bench(
+        tgp, torch, args.form_steps, json.loads(args.adj_cfg) if args.adj_cfg else None)
+    if diff:
+        print(f"differentiation: {json.dumps(diff)}", file=sys.stderr, flush=True)
+    dpar = None if args.no_data_parallel else data_parallel_bench(tgp, torch, args.form_steps)
+    if dpar:
+        print(f"data_parallel: {json.dumps(dpar)}", file=sys.stderr, flush=True)
     exchange = None if args.no_exchange else exchange_bench(tgp, torch, w, args.workload, args.exchange_steps)
     generation = None if args.no_generation else generation_bench(tgp, torch)
     classification = None if args.no_classification else classification_bench(tgp, torch)
-
-    # ---- roofline of the evaluation kernel ----
-    if args.no_roofline:
-        costs = [float("nan")] * len(OP_NAMES)
-    else:
-        costs = op_costs(tgp)
-    t = w.type
-    fn = t >= 2
-    ops = w.value[fn].astype(np.int64)
-    counts = np.bincount(ops, minlength=len(OP_NAMES))
-    ops_per_point = float(np.dot(counts, costs)) + 2.0 * w.P * w.n_out
-    algo_ops = ops_per_point * w.D
-    eval_ms = eval_ms_total / max(launches, 1)
-    achieved = algo_ops / (eval_ms * 1e-3)
-    src_hash = eval_source_hash()
-    traffic = stored_traffic(args.workload, src_hash)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "Top/s",
-                "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
-                "kernel": "eval_kernel", "kernel_ms": eval_ms, "algo_ops_per_launch": algo_ops,
-                "op_cost": {n: round(c, 3) for n, c in zip(OP_NAMES, costs)},
-                "eval_source_hash": src_hash}
 
     out = {"metric": METRIC, "value": value, "unit": "GPops/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"{args.workload}: {w.desc}", "P": w.P, "Lmax": w.Lmax, "V": w.V, "D": w.D,
                       "n_out": w.n_out, "sum_len": sum_len, "schedule": cfg, "wall_s": t_wall},
-           "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "exchange": exchange,
-           "generation": generation, "classification": classification}
+           "roofline": roofline, "cpu_baseline": cpu, "forms": forms, "differentiation": diff,
+           "data_parallel": dpar, "exchange": exchange, "generation": generation,
+           "classification": classification}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -101,7 +101,8 @@ enum { TGP_MODE_AUTO = 0, TGP_MODE_TREE_MAJOR = 1, TGP_MODE_POINT_MAJOR = 2,
  * per tile) or, with TGP_FLAG_STATIC_ORDER, dealt round-robin in snake
  * order without atomics. */
 enum { TGP_FLAG_NO_TAIL_CHECK = 1,     /* skip reading the NaN padding after len */
-       TGP_FLAG_STATIC_ORDER = 2 };
+       TGP_FLAG_STATIC_ORDER = 2,
+       TGP_FLAG_ADJ_RECOMPUTE = 4 };   /* gradient calls: recompute sweep for every tree */
 typedef struct tgp_cfg {
   int32_t mode;             /* TGP_MODE_*                                           */
   int32_t block_waves;      /* waves per workgroup: 1, 2 or 4                       */
@@ -111,7 +112,11 @@ typedef struct tgp_cfg {
 } tgp_cfg;
 
 /* Bytes of workspace needed by any call on these shapes (n_out outputs;
- * want_grad != 0 adds room for tgp_eval_mse_grad). Returns 0 for shapes
+ * want_grad != 0 adds room for tgp_eval_mse_grad). data may be NULL only to
+ * size a tgp_plan call: evaluation calls keep one float64 fitness partial
+ * per (tree, tile of 256 points; 128 for gradient calls), which the
+ * finalize step adds in a fixed order, so a call's fitness values are
+ * bitwise reproducible whatever order its waves ran in. Returns 0 for shapes
  * the library rejects. */
 size_t tgp_workspace_bytes(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
                            int32_t want_grad);
@@ -157,6 +162,14 @@ tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp
 
 /* Fitness and its gradient (not in the paper; reverse-mode sweep over the
  * prefix tree with subtree values recomputed, nothing stored per point).
+ * The sweep walks each tree by heavy paths: one run of the program gives the
+ * fitness and the values along the root's path of larger children, and every
+ * smaller child's subtree is run once more for its own path. A tree whose
+ * sweep would hold more values per lane at once than the sweep's LDS budget
+ * (16 at 2 points per lane, 12 at 4; deep trees) is swept
+ * instead node by node, re-running each function child's subtree;
+ * TGP_FLAG_ADJ_RECOMPUTE in cfg->flags sends every tree that way. Both give
+ * the same gradient up to the order of float32 sums.
  * grad_mse: optional device float32 [P], upstream dL/dmse_t (NULL = all ones).
  * grad_value: optional device float32 [P][row_stride], overwritten with
  *   dL/dvalue (non-zero only at constant nodes; zero elsewhere and for

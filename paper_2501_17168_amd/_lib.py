@@ -20,6 +20,8 @@ TGP_E_HIP = -6
 
 MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT = 0, 1, 2, 3
 FLAG_NO_TAIL_CHECK = 1
+FLAG_STATIC_ORDER = 2
+FLAG_ADJ_RECOMPUTE = 4
 
 # symbols the header declares; the CPU tests check that each one is exported
 EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output", "tgp_eval_accuracy",

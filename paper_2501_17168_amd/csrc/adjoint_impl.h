@@ -74,6 +74,25 @@ __device__ __forceinline__ void partials(int op, float a, float b, float& da, fl
 }
 
 
+// The same partial derivatives when the node's own value v is at hand (own):
+// exp, tanh and tan take it instead of calling the library again. v came from
+// the same float32 argument through the same function, so the result is
+// bitwise the one partials() gives.
+__device__ __forceinline__ void partials_own(int op, float a, float b, float v, bool own, float& da, float& db) {
+  if (own && op == kOpExp) {
+    da = (a >= -kExpClamp && a <= kExpClamp) ? v : 0.0f;
+    db = 0.0f;
+  } else if (own && op == kOpTanh) {
+    da = 1.0f - v * v;
+    db = 0.0f;
+  } else if (own && op == kOpTan) {
+    da = 1.0f + v * v;
+    db = 0.0f;
+  } else {
+    partials(op, a, b, da, db);
+  }
+}
+
 template <int K, int VM>
 struct AdjState {
   Regs<K, VM, 1> s;
@@ -157,10 +176,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
 #pragma unroll
     for (int j = 0; j < K; ++j) st.gx[v][j] = 0.0f;
 
+  bool swept = false;  // this wave swept a tree (otherwise it has no grad_X to add)
   for (int64_t t = t0; t < t1; ++t) {
     const int32_t* inf = a.info + t * kInfoStride;
     const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
     if (status != 0) continue;
+    if (__builtin_amdgcn_readfirstlane(inf[kInfoAdjFmt]) != kAdjFmtRecompute) continue;
+    swept = true;
     const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
     const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
     const int plen = __builtin_amdgcn_readfirstlane(inf[kInfoProgLen]);
@@ -262,7 +284,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
           }
         }
         sse = wave_sum_f64(sse);
-        if (lane == 0) unsafeAtomicAdd(&a.acc[t], sse);
+        if (lane == 0) a.part[tile * a.P + t] = sse;
         if (nint == 0) {  // the tree is a single leaf
           const uint2 ins = a.prog[t * a.pstride];
           const int src = word_case(ins.x) - kLD;
@@ -325,7 +347,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
   }
 
   // ---- grad_X: one atomic per (lane, point, variable) for the whole run ----
-  if (a.grad_X) {
+  if (a.grad_X && swept) {
 #pragma unroll
     for (int v = 0; v < VM; ++v) {
       if (v < a.V) {
@@ -339,8 +361,244 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
   }
 }
 
+// Heavy-path sweep (trees whose records are in the heavy-path format).
+// Per (tree, tile): one run of the whole program gives the output, the
+// fitness partial and the captures of the root path; the records then walk
+// each path top down. At a record the children's values are popped from the
+// capture stack (light child on top, heavy child below it), the partials
+// formed, leaves take their adjoints, the light child's adjoint waits on the
+// pending stack, and the heavy child's adjoint and value become the current
+// ones. At the end of a path the most recently parked light child is taken
+// and its code range run once at its light depth, which captures its own
+// path and leaves its value in A. Every function node is thus interpreted
+// once per path head above it (the root's run included), instead of once
+// per function ancestor. The next record is loaded while the current one is
+// worked on.
+// Wave LDS: spill slots 4..7, then `cap` values (captures from the bottom,
+// pending adjoints from the top), then `cap` ints of pending code ranges.
+__device__ __forceinline__ uint4 load_path_record(rec_ptr p) { return make_uint4(p[0], p[1], p[2], p[3]); }
+
+template <int K, int VM>
+__global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
+  extern __shared__ float s_lds[];
+  constexpr int kTile = K * kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int W = blockDim.x / kWave;
+  const int CAP = a.cap;
+  const int per_wave = (kMaxSlots - kRegSlots + CAP) * K * kWave;
+  float* spill = s_lds + wv * per_wave + lane;
+  float* vals = spill + (kMaxSlots - kRegSlots) * K * kWave;
+  int* pinfo = (int*)(s_lds + W * per_wave) + wv * CAP;
+
+  const int64_t b = blockIdx.x;
+  const int g = (int)(b % a.ngroups);
+  const int tile = g * W + wv;
+  if (tile >= a.ntiles) return;
+  const int64_t t0 = (b / a.ngroups) * a.tpu;
+  const int64_t t1 = min(a.P, t0 + a.tpu);
+  const int64_t p0 = (int64_t)tile * kTile + lane;
+
+  AdjState<K, VM> st;
+  Regs<K, VM, 1>& s = st.s;
+  load_x_adj<K, VM>(a, s, p0);
+#pragma unroll
+  for (int v = 0; v < VM; ++v)
+#pragma unroll
+    for (int j = 0; j < K; ++j) st.gx[v][j] = 0.0f;
+
+  bool swept = false;  // this wave swept a tree (otherwise it has no grad_X to add)
+  for (int64_t t = t0; t < t1; ++t) {
+    const int32_t* inf = a.info + t * kInfoStride;
+    const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
+    if (status != 0) continue;
+    if (__builtin_amdgcn_readfirstlane(inf[kInfoAdjFmt]) != kAdjFmtPath) continue;
+    swept = true;
+    const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
+    const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
+    const int plen = __builtin_amdgcn_readfirstlane(inf[kInfoProgLen]);
+    const float gt = a.grad_mse ? a.grad_mse[t] : 1.0f;
+    prog_ptr prog = (prog_ptr)(a.prog + t * a.pstride);
+    rec_ptr recs = (rec_ptr)(a.adj + t * (int64_t)a.Lmax * kAdjWords);
+
+    float gbar[K], cur[K], curv[K];
+    int csp = 0, psp = 0, q = 0;
+    // the run ahead: the whole program but its END (the root's), or a light head's code range
+    uint32_t rs = 0, rl = (uint32_t)(plen - 1);
+    int rlev = 0;
+    bool root = true;
+    uint4 rn = make_uint4(0u, 0u, 0u, 0u);  // the next record, loaded ahead
+    for (;;) {
+      if (root) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          s.A[j] = 0.0f;
+          s.O[0][j] = 0.0f;
+        }
+        if (nint > 0) rn = load_path_record(recs);
+      }
+      // the kernel's one interpreter call site
+      run_program<K, VM, 1, true, true>(prog + rs, s, spill, (int)rl, vals, &csp, rlev, CAP - psp);
+      if (root) {
+        root = false;
+        // ---- forward: output, fitness partial, output adjoint ----
+        double sse = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int64_t p = p0 + j * kWave;
+          const float out = nmodi ? s.O[0][j] : s.A[j];
+          gbar[j] = 0.0f;
+          if (p < a.D) {
+            const float e = out - a.Y[p];
+            sse += (double)(e * e);
+            gbar[j] = gt * 2.0f * e * a.inv_D;
+          }
+        }
+        sse = wave_sum_f64(sse);
+        if (lane == 0) a.part[tile * a.P + t] = sse;
+        if (nint == 0) {  // the tree is a single leaf
+          const uint2 ins = a.prog[t * a.pstride];
+          const int src = word_case(ins.x) - kLD;
+          if (src >= kSrcX0)
+            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
+          else
+            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
+          break;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+      }
+      // the run's value is the current node's own value: the root's, or the light head's
+#pragma unroll
+      for (int j = 0; j < K; ++j) curv[j] = s.A[j];
+      // ---- records down to the end of a path ----
+      bool run_next = false;
+      while (q < nint) {
+        const uint32_t w0 = rn.x, w1 = rn.y, w2 = rn.z, w3 = rn.w;
+        ++q;
+        const int op = w0 & 15, ar = (w0 >> 4) & 3, modi = (w0 >> 6) & 1;
+        const int ka = (w0 >> 7) & 3, kb = (w0 >> 9) & 3;
+        const int va_var = (w0 >> 11) & 15, vb_var = (w0 >> 15) & 15;
+        const int eop = (w0 >> 19) & 1, has_light = (w0 >> 20) & 1, has_heavy = (w0 >> 21) & 1;
+        const uint32_t node_a = w0 >> 22, node_b = w3;
+        // children values: the light child's capture is on top, the heavy child's below it
+        float vl[K], vh[K], va[K], vb[K];
+        if (has_light) {
+          --csp;
+          const float* src = vals + csp * (K * kWave);
+#pragma unroll
+          for (int j = 0; j < K; ++j) vl[j] = src[j * kWave];
+        }
+        if (has_heavy) {
+          --csp;
+          const float* src = vals + csp * (K * kWave);
+#pragma unroll
+          for (int j = 0; j < K; ++j) vh[j] = src[j * kWave];
+        }
+        // the next record, loaded while this one is worked on
+        if (q < nint) rn = load_path_record(recs + q * kPathWords);
+        if (ka == kPathHeavy) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) va[j] = vh[j];
+        } else if (ka == kPathLight) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) va[j] = vl[j];
+        } else {
+          leaf_value<K, VM>(s, ka, va_var, w1, va);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) vb[j] = 0.0f;
+        if (ar == 2) {
+          if (kb == kPathHeavy) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) vb[j] = vh[j];
+          } else if (kb == kPathLight) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) vb[j] = vl[j];
+          } else {
+            leaf_value<K, VM>(s, kb, vb_var, w2, vb);
+          }
+        }
+        float a1[K], a2[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          float da, db;
+          partials_own(op, va[j], vb[j], curv[j], !modi, da, db);
+          const float base = modi ? gbar[j] : cur[j];
+          a1[j] = base * da;
+          a2[j] = base * db;
+          if (modi) {  // the handed-up value is the rightmost child's
+            if (ar == 2) a2[j] += cur[j];
+            else a1[j] += cur[j];
+          }
+        }
+        // leaves take their adjoints now
+        if (ka == kKindVar || ka == kKindConst) leaf_adjoint<K, VM>(a, st, t, p0, lane, ka, va_var, node_a, a1);
+        if (ar == 2 && (kb == kKindVar || kb == kKindConst))
+          leaf_adjoint<K, VM>(a, st, t, p0, lane, kb, vb_var, node_b, a2);
+        // the light child waits: its adjoint on the pending stack, its code range beside it
+        if (has_light) {
+          const float* al = (ka == kPathLight) ? a1 : a2;
+          if (csp + psp + 1 <= CAP) {
+            float* dadj = vals + (CAP - 1 - psp) * (K * kWave);
+#pragma unroll
+            for (int j = 0; j < K; ++j) dadj[j * kWave] = al[j];
+            pinfo[psp] = (int)((ka == kPathLight) ? w1 : w2);
+          }
+          ++psp;
+        }
+        if (has_heavy) {
+          const float* ah = (ka == kPathHeavy) ? a1 : a2;
+#pragma unroll
+          for (int j = 0; j < K; ++j) {
+            cur[j] = ah[j];
+            curv[j] = vh[j];
+          }
+        }
+        if (eop) {
+          if (psp == 0) break;  // the tree's last path
+          --psp;
+          const float* sadj = vals + (CAP - 1 - psp) * (K * kWave);
+#pragma unroll
+          for (int j = 0; j < K; ++j) cur[j] = sadj[j * kWave];
+          const uint32_t info = (uint32_t)__builtin_amdgcn_readfirstlane(pinfo[psp]);
+          rs = info & 0xfffu;
+          rl = (info >> 12) & 0xfffu;
+          rlev = (int)((info >> 24) & 15u);
+          run_next = true;
+          break;
+        }
+      }
+      if (!run_next) break;
+    }
+  }
+
+  // ---- grad_X: one atomic per (lane, point, variable) for the whole run ----
+  if (a.grad_X && swept) {
+#pragma unroll
+    for (int v = 0; v < VM; ++v) {
+      if (v < a.V) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const int64_t p = p0 + j * kWave;
+          if (p < a.D) atomicAdd(&a.grad_X[(int64_t)v * a.ldx + p], st.gx[v][j]);
+        }
+      }
+    }
+  }
+}
+
+// Both sweeps: heavy-path trees, then the trees whose sweep would not fit the
+// heavy-path kernel's LDS budget (each kernel skips the other's trees).
 template <int K, int VM>
 hipError_t launch_adjoint_kv(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s) {
+  if (a.cap > 0) {
+    const size_t lds_p = (size_t)block_waves * ((kMaxSlots - kRegSlots + a.cap) * K * kWave * sizeof(float) +
+                                                a.cap * sizeof(int));
+    adjoint_path_kernel<K, VM><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds_p, s>>>(a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const size_t lds = (size_t)block_waves * (kMaxSlots - kRegSlots + a.pend_slots) * K * kWave * sizeof(float);
   adjoint_kernel<K, VM><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds, s>>>(a);
   return hipGetLastError();

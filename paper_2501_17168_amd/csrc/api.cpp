@@ -2,8 +2,8 @@
 //
 // Every evaluation call enqueues, on the caller's stream and without any
 // allocation or synchronisation:
-//   plan (validate, plan figures, compile programs, zero accumulators and,
-//         for the persistent schedule, the bucket counters and work queues)
+//   plan (validate, plan figures, compile programs and, for the persistent
+//         schedule, zero the bucket counters and work queues)
 //   -> [order trees by length bucket, persistent mode only]
 //   -> evaluation kernel -> finalize (fitness and per-tree status).
 #include <hip/hip_runtime.h>
@@ -26,14 +26,15 @@ constexpr int kCounters = 64 + kMaxTileQueues * kQueueStride;  // hist[16] | cur
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t info, acc, order, counters, prog, gwork, total;
+  size_t info, part, order, counters, prog, gwork, total;
 };
 
-Layout layout(int64_t P, int Lmax, int64_t grad_bytes) {
+// part_tiles: point tiles the fitness partials [tiles][P] must hold (0 for plan-only calls)
+Layout layout(int64_t P, int Lmax, int64_t part_tiles, int64_t grad_bytes) {
   Layout L{};
   size_t off = 0;
   L.info = off; off = align_up(off + (size_t)P * kInfoStride * sizeof(int32_t));
-  L.acc = off; off = align_up(off + (size_t)P * sizeof(double));
+  L.part = off; off = align_up(off + (size_t)P * part_tiles * sizeof(double));
   L.order = off; off = align_up(off + (size_t)P * sizeof(int32_t));
   L.counters = off; off = align_up(off + kCounters * sizeof(int32_t));
   L.prog = off; off = align_up(off + (size_t)P * prog_stride(Lmax) * sizeof(uint2));
@@ -75,6 +76,20 @@ tgp_status check_ws(void* ws, size_t ws_bytes, size_t need) {
 
 int vm_for(int V) { return V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : 16; }
 
+// Point tiles of the smallest tile a call may use: 64 lanes x 4 points for the
+// forward kernels, x 2 points for the adjoint.
+int64_t part_tiles(const tgp_data* d, bool grad) {
+  const int64_t tile = grad ? 128 : 256;
+  return (d->D + tile - 1) / tile;
+}
+
+// Finalize segments per tree: about 32 tiles per thread, at most 16 threads per tree.
+int fin_segs(int64_t ntiles) {
+  int s = 1;
+  while (s < 16 && (int64_t)s * 32 < ntiles) s *= 2;
+  return s;
+}
+
 // adjoint records: one 32-byte record per function node, Lmax slots per tree
 int64_t grad_work_bytes(const tgp_pop* pop, const tgp_data* d) {
   (void)d;
@@ -91,6 +106,13 @@ int pend_slots_for(int Lmax) {
   return std::max(1, lg);
 }
 
+// Values per wave the heavy-path adjoint sweep holds in LDS (captures and waiting light
+// children), by points per lane: 16 at 2 points (10 KB per wave with the spill slots; it
+// covers every tree of the depth-8 ramped populations), 12 at 4 (16 KB per wave: ten
+// waves per CU; 96% of depth-8 ramped trees). Trees whose sweep needs more go to the
+// recompute sweep.
+int adj_path_cap(int K) { return K == 2 ? 16 : 12; }
+
 int device_cus() {
   static int cus = -1;
   static std::mutex m;
@@ -106,11 +128,10 @@ int device_cus() {
   return cus;
 }
 
-// Resident waves per CU the evaluation kernel holds (4 SIMDs x its occupancy by K).
-int resident_per_cu(int K) { return K >= 16 ? 8 : (K >= 8 ? 12 : 20); }
 
-// Fill unset fields of a launch configuration.
-tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_out, bool grad) {
+// Fill unset fields of a launch configuration (for a forward call with these
+// outputs and prediction flag).
+tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, bool pred) {
   tgp_cfg c{};
   if (in) c = *in;
   if (!in || c.mode == TGP_MODE_AUTO) {
@@ -140,7 +161,8 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
     } else {
       // persistent: group trees only when the chunks still fill every resident wave slot;
       // a short queue of long chunks leaves lone waves exposed to program-fetch latency
-      const int64_t slots = (int64_t)device_cus() * resident_per_cu(c.points_per_lane);
+      const int64_t slots = (int64_t)device_cus() *
+                            eval_resident_waves(c.points_per_lane, vm_for(d->V), n_out, pred, c.block_waves);
       c.trees_per_unit = (int)std::min<int64_t>(8, std::max<int64_t>(1, pop->P * ntiles / slots));
     }
   }
@@ -152,7 +174,7 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
 // counters when the order is wanted; nothing else reads them.
 tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, char* ws,
                         const Layout& L, int32_t* out_info, int32_t* out_status, bool want_order,
-                        hipStream_t s, bool want_adj = false, int64_t n_queues = 0) {
+                        hipStream_t s, bool want_adj = false, int64_t n_queues = 0, int adj_cap = 0) {
   int32_t* counters = (int32_t*)(ws + L.counters);
   PlanArgs pa{};
   pa.type = pop->type;
@@ -167,8 +189,8 @@ tgp_status enqueue_plan(const tgp_pop* pop, int V, int n_out, const tgp_cfg& c, 
   pa.info = (int32_t*)(ws + L.info);
   pa.prog = (uint2*)(ws + L.prog);
   pa.pstride = prog_stride(pop->Lmax);
-  pa.acc = (double*)(ws + L.acc);
   pa.adj = want_adj ? (uint32_t*)(ws + L.gwork) : nullptr;
+  pa.adj_cap = want_adj ? adj_cap : 0;
   pa.out_info = out_info;
   pa.out_status = out_status;
   pa.zero = want_order ? counters : nullptr;
@@ -194,11 +216,11 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   st = check_data(d, mse != nullptr);
   if (st) return st;
   if (pred && ldp < d->D) return TGP_E_SHAPE;
-  const Layout L = layout(pop->P, pop->Lmax, 0);
+  const Layout L = layout(pop->P, pop->Lmax, part_tiles(d, false), 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   if (pop->P == 0) return TGP_OK;
-  const tgp_cfg c = resolve(cfg, pop, d, n_out, false);
+  const tgp_cfg c = resolve(cfg, pop, d, n_out, false, pred != nullptr);
   char* w = (char*)ws;
   const int K = c.points_per_lane;
   const int64_t tile = 64LL * K;
@@ -222,7 +244,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   ea.info = (const int32_t*)(w + L.info);
   ea.prog = (const uint2*)(w + L.prog);
   ea.pstride = prog_stride(pop->Lmax);
-  ea.acc = (double*)(w + L.acc);
+  ea.part = (double*)(w + L.part);
   ea.pred = pred;
   ea.ldp = ldp;
   ea.P = pop->P;
@@ -238,7 +260,8 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   } else if (c.mode == TGP_MODE_POINT_MAJOR) {
     grid = ((pop->P + ea.tpu - 1) / ea.tpu) * ea.ngroups;
   } else {
-    const int64_t cap = (int64_t)device_cus() * resident_per_cu(K);
+    // persistent waves: as many as the chip holds at once for this instantiation
+    const int64_t cap = (int64_t)device_cus() * eval_resident_waves(K, vm_for(d->V), n_out, pred != nullptr, bw);
     const int64_t chunks = (pop->P + ea.tpu - 1) / ea.tpu;
     ea.wpt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap / ntiles, chunks));
     ea.dynamic = (c.flags & TGP_FLAG_STATIC_ORDER) ? 0 : 1;
@@ -246,7 +269,7 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
     ea.nsub = (int32_t)std::max<int64_t>(1, std::min<int64_t>({8, kMaxTileQueues / ntiles, (int64_t)ea.wpt}));
     grid = (ntiles * ea.wpt + bw - 1) / bw;
   }
-  const int NO = (n_out > 1) ? kMaxOut : 1;
+  const int NO = n_out;
   void* tok = nullptr;
   profile_before(s, &tok);
   const hipError_t le = launch_eval(ea, K, vm_for(d->V), NO, pred != nullptr, bw, grid, s);
@@ -254,7 +277,9 @@ tgp_status forward(const tgp_pop* pop, const tgp_data* d, const tgp_cfg* cfg, in
   if (le != hipSuccess) return TGP_E_HIP;
   FinalArgs fa{};
   fa.info = ea.info;
-  fa.acc = ea.acc;
+  fa.part = ea.part;
+  fa.ntiles = (int32_t)ntiles;
+  fa.segs = fin_segs(ntiles);
   fa.P = pop->P;
   fa.inv_D = 1.0 / (double)d->D;
   fa.mse = mse;
@@ -274,7 +299,7 @@ __attribute__((visibility("default"))) size_t tgp_workspace_bytes(const tgp_pop*
   if (n_out < 1 || n_out > kMaxOut) return 0;
   int64_t gb = 0;
   if (want_grad && data) gb = grad_work_bytes(pop, data);
-  return layout(pop->P, pop->Lmax, gb).total;
+  return layout(pop->P, pop->Lmax, data ? part_tiles(data, want_grad != 0) : 0, gb).total;
 }
 
 __attribute__((visibility("default"))) tgp_status tgp_plan(const tgp_pop* pop, int32_t V, int32_t n_out,
@@ -285,7 +310,7 @@ __attribute__((visibility("default"))) tgp_status tgp_plan(const tgp_pop* pop, i
   if (st) return st;
   if (V < 1 || n_out < 1) return TGP_E_SHAPE;
   if (V > kMaxV || n_out > kMaxOut) return TGP_E_UNSUPPORTED;
-  const Layout L = layout(pop->P, pop->Lmax, 0);
+  const Layout L = layout(pop->P, pop->Lmax, 0, 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   if (pop->P == 0) return TGP_OK;
@@ -331,7 +356,7 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   st = check_data(data, true);
   if (st) return st;
   if (data->n_out != 1) return TGP_E_SHAPE;
-  const Layout L = layout(pop->P, pop->Lmax, grad_work_bytes(pop, data));
+  const Layout L = layout(pop->P, pop->Lmax, part_tiles(data, true), grad_work_bytes(pop, data));
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   if (pop->P == 0) return TGP_OK;
@@ -339,7 +364,11 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (cfg) c = *cfg;
   if (!cfg || c.mode == TGP_MODE_AUTO) {
     tgp_cfg cached{};
-    if (autotune_lookup(pop, data, 1, true, &cached)) c = cached;
+    if (autotune_lookup(pop, data, 1, true, &cached)) {
+      const int flags = c.flags;
+      c = cached;
+      c.flags |= flags;
+    }
   }
   c.mode = TGP_MODE_POINT_MAJOR;
   // 2 or 4 points per lane: at 2 the adjoint's registers and LDS halve and twice the waves fit
@@ -348,7 +377,8 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   // residency, and small workgroups pack it best
   if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 1;
   char* w = (char*)ws;
-  st = enqueue_plan(pop, data->V, 1, c, w, L, nullptr, nullptr, false, stream, true);
+  const int cap = (c.flags & TGP_FLAG_ADJ_RECOMPUTE) ? 0 : adj_path_cap(c.points_per_lane);
+  st = enqueue_plan(pop, data->V, 1, c, w, L, nullptr, nullptr, false, stream, true, 0, cap);
   if (st) return st;
   if (launch_zero_f32(grad_value, pop->P, pop->row_stride, pop->row_stride, stream) != hipSuccess) return TGP_E_HIP;
   if (launch_zero_f32(grad_X, data->V, data->D, data->ldx, stream) != hipSuccess) return TGP_E_HIP;
@@ -373,7 +403,7 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   aa.pstride = prog_stride(pop->Lmax);
   aa.adj = (const uint32_t*)(w + L.gwork);
   aa.Lmax = pop->Lmax;
-  aa.acc = (double*)(w + L.acc);
+  aa.part = (double*)(w + L.part);
   aa.grad_mse = grad_mse;
   aa.grad_value = grad_value;
   aa.gv_stride = pop->row_stride;
@@ -383,6 +413,7 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   aa.ngroups = (int32_t)ngroups;
   aa.tpu = (int32_t)tpu;
   aa.pend_slots = pend_slots_for(pop->Lmax);
+  aa.cap = cap;
   const int64_t grid = ((pop->P + tpu - 1) / tpu) * ngroups;
   void* tok = nullptr;
   profile_before(stream, &tok);
@@ -391,7 +422,9 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (le != hipSuccess) return TGP_E_HIP;
   FinalArgs fa{};
   fa.info = aa.info;
-  fa.acc = aa.acc;
+  fa.part = aa.part;
+  fa.ntiles = (int32_t)ntiles;
+  fa.segs = fin_segs(ntiles);
   fa.P = pop->P;
   fa.inv_D = 1.0 / (double)data->D;
   fa.mse = mse;
@@ -409,7 +442,8 @@ __attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* po
   st = check_data(data, true);
   if (st) return st;
   if (want_grad && n_out != 1) return TGP_E_SHAPE;
-  const Layout L = layout(pop->P, pop->Lmax, want_grad ? grad_work_bytes(pop, data) : 0);
+  const Layout L = layout(pop->P, pop->Lmax, part_tiles(data, want_grad != 0),
+                          want_grad ? grad_work_bytes(pop, data) : 0);
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
   return autotune_run(pop, data, n_out, want_grad != 0, out, ws, ws_bytes, stream);

@@ -27,7 +27,8 @@
 // the persistent queue's next chunk is requested one chunk ahead.
 //
 // Reduction: per lane, float32 residual and square; pairwise lane sum and
-// DPP wave sum in float32; one float64 atomic per (wave, tree).
+// DPP wave sum in float32; one float64 partial per (tree, tile), written by
+// lane 0 and summed in a fixed order by the finalize kernel.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -105,13 +106,15 @@ __device__ __forceinline__ unsigned long long uniform64(uint2 v) {
 //
 // Fitness reduction (accuracy: hit counts, exact): squared residuals in float32, summed pairwise per lane
 // and over the wave by DPP (all terms non-negative: relative error below
-// (log2 K + 6) float32 ulp, under 6e-7), then added in float64 across
-// waves. If the float32 wave sum overflows, the tile is summed again in
-// float64 (terms that are themselves infinite give the same result).
+// (log2 K + 6) float32 ulp, under 6e-7). If the float32 wave sum overflows,
+// the tile is summed again in float64 (terms that are themselves infinite
+// give the same result). The tile's sum is stored as the (tree, tile)
+// partial; the finalize kernel adds a tree's partials in float64 in a fixed
+// order, so the fitness does not depend on which wave finished first.
 template <int K, int VM, int NO, bool PRED, class Between>
 __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s, const TileY<K, NO>& ty,
                                           float* spill, uint32_t hdr, unsigned long long first, int64_t p0,
-                                          int lane, Between between) {
+                                          int64_t tile, int lane, Between between) {
   const int64_t t = hdr & kHdrTree;
   if (hdr & kHdrInvalid) {
     between();
@@ -172,7 +175,7 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
       hits += (p < a.D && (float)cls == ty.y[0][j]) ? 1.0f : 0.0f;
     }
     const float tot = wave_sum_f32(hits);
-    if (lane == 0) unsafeAtomicAdd(&a.acc[t], (double)tot);
+    if (lane == 0) a.part[tile * a.P + t] = (double)tot;
     return;
   }
   float lane_sum = 0.0f;
@@ -206,7 +209,7 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
     }
     tot = wave_sum_f64(l64);
   }
-  if (lane == 0) unsafeAtomicAdd(&a.acc[t], tot);
+  if (lane == 0) a.part[tile * a.P + t] = tot;
 }
 
 // Positions of the trees one wave evaluates on its tile.
@@ -335,7 +338,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
       h1 = k1 < a.P ? uniform(vh1) : kHdrInvalid;
       if (!(h1 & kHdrInvalid)) vf1 = bcast_load_u64(first_ptr(h1));
     };
-    eval_tree<K, VM, NO, PRED>(a, s, ty, spill, hdr, first, p0, lane, between);
+    eval_tree<K, VM, NO, PRED>(a, s, ty, spill, hdr, first, p0, tile, lane, between);
     if (k1 >= a.P) break;
     hdr = h1;
     first = (h1 & kHdrInvalid) ? 0ull : uniform64(vf1);
@@ -351,10 +354,48 @@ inline hipError_t launch_eval_t(const EvalArgs& a, int block_waves, int64_t grid
   return hipGetLastError();
 }
 
+// Workgroups of block_waves waves that one CU holds at once for this instantiation
+// (registers, LDS and the launch bound), or 0 when the runtime cannot say.
+template <int K, int VM, int NO, bool PRED>
+inline int occupancy_eval_t(int block_waves) {
+  const size_t lds = (size_t)block_waves * kLdsFloatsPerWave<K> * sizeof(float);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_kernel<K, VM, NO, PRED>, block_waves * kWave, lds) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
+
+template <int K, int VM, int NO>
+inline hipError_t launch_eval_kvo(const EvalArgs& a, bool pred, int bw, int64_t grid, hipStream_t s) {
+  return pred ? launch_eval_t<K, VM, NO, true>(a, bw, grid, s) : launch_eval_t<K, VM, NO, false>(a, bw, grid, s);
+}
+
+template <int K, int VM, int NO>
+inline int occupancy_eval_kvo(bool pred, int bw) {
+  return pred ? occupancy_eval_t<K, VM, NO, true>(bw) : occupancy_eval_t<K, VM, NO, false>(bw);
+}
+
+// The output accumulators are instantiated for exactly n_out outputs (1..4), so a
+// three-output population carries three accumulators, not four.
 template <int K, int VM>
 hipError_t launch_eval_kv(const EvalArgs& a, int NO, bool pred, int bw, int64_t grid, hipStream_t s) {
-  if (NO == 1) return pred ? launch_eval_t<K, VM, 1, true>(a, bw, grid, s) : launch_eval_t<K, VM, 1, false>(a, bw, grid, s);
-  return pred ? launch_eval_t<K, VM, kMaxOut, true>(a, bw, grid, s) : launch_eval_t<K, VM, kMaxOut, false>(a, bw, grid, s);
+  switch (NO) {
+    case 1: return launch_eval_kvo<K, VM, 1>(a, pred, bw, grid, s);
+    case 2: return launch_eval_kvo<K, VM, 2>(a, pred, bw, grid, s);
+    case 3: return launch_eval_kvo<K, VM, 3>(a, pred, bw, grid, s);
+    default: return launch_eval_kvo<K, VM, kMaxOut>(a, pred, bw, grid, s);
+  }
+}
+
+template <int K, int VM>
+int occupancy_eval_kv(int NO, bool pred, int bw) {
+  switch (NO) {
+    case 1: return occupancy_eval_kvo<K, VM, 1>(pred, bw);
+    case 2: return occupancy_eval_kvo<K, VM, 2>(pred, bw);
+    case 3: return occupancy_eval_kvo<K, VM, 3>(pred, bw);
+    default: return occupancy_eval_kvo<K, VM, kMaxOut>(pred, bw);
+  }
 }
 
 }  // namespace tgp

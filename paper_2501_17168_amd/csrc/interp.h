@@ -101,9 +101,15 @@ typedef const __attribute__((address_space(4))) unsigned long long* prog_ptr;
 // which has no END of its own); otherwise the program runs up to its END.
 // run_from takes the first instruction word already loaded (`first`, equal
 // to prog[0]); run_program loads it.
-template <int K, int VM, int NO, bool BOUNDED = false>
+// With CAPTURE (the adjoint's runs), after every word whose capture level
+// (tgp_isa.h) equals `cap_level`, A is pushed on the wave's capture stack:
+// value c sits at cap[c * K * 64 + j * 64] (cap offset by the lane), *csp
+// counts the values, and pushes beyond cap_limit are dropped (the plan sizes
+// every tree's sweep within the limit).
+template <int K, int VM, int NO, bool BOUNDED = false, bool CAPTURE = false>
 __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first, Regs<K, VM, NO>& s, float* spill,
-                                         int count = 0) {
+                                         int count = 0, float* cap = nullptr, int* csp = nullptr, int cap_level = 0,
+                                         int cap_limit = 0) {
   if (BOUNDED && count <= 0) return;
   // `first` is wave-uniform; say so, so that it can live in scalar registers
   unsigned long long ins = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)first) |
@@ -276,6 +282,17 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
         }
       }
     }
+    if constexpr (CAPTURE) {
+      if ((w & kCapFlag) && capture_level(w) == cap_level) {
+        const int c = *csp;
+        if (c < cap_limit) {
+          float* dst = cap + c * (K * kWave);
+#pragma unroll
+          for (int j = 0; j < K; ++j) dst[j * kWave] = s.A[j];
+        }
+        *csp = c + 1;
+      }
+    }
     unsigned long long n2 = nxt;
     asm volatile("" : "+s"(n2));
     ins = n2;
@@ -283,10 +300,12 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
   }
 }
 
-template <int K, int VM, int NO, bool BOUNDED = false>
-__device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, float* spill, int count = 0) {
+template <int K, int VM, int NO, bool BOUNDED = false, bool CAPTURE = false>
+__device__ __forceinline__ void run_program(prog_ptr prog, Regs<K, VM, NO>& s, float* spill, int count = 0,
+                                            float* cap = nullptr, int* csp = nullptr, int cap_level = 0,
+                                            int cap_limit = 0) {
   if (BOUNDED && count <= 0) return;
-  run_from<K, VM, NO, BOUNDED>(prog, prog[0], s, spill, count);
+  run_from<K, VM, NO, BOUNDED, CAPTURE>(prog, prog[0], s, spill, count, cap, csp, cap_level, cap_limit);
 }
 
 // 64-bit DPP move: row_shr / row_bcast as in the GCN data-parallel

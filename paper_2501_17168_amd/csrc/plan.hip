@@ -44,6 +44,9 @@ __device__ __forceinline__ int rec_modi(int r) { return ((r >> 8) & 15) - 1; }
 __device__ __forceinline__ int rec_var(int r) { return (r >> 12) & 31; }
 // set on the later-visited child of a node whose children are both function nodes (adjoint order)
 constexpr int kRecPop = 1 << 20;
+// set on the light child of a node whose children are both function nodes: the smaller one, which
+// the code evaluates second (ties: the second child)
+constexpr int kRecLight = 1 << 21;
 
 __device__ __forceinline__ bool is_intf(float x) { return isfinite(x) && x == floorf(x); }
 
@@ -155,17 +158,123 @@ __device__ __forceinline__ int fused_case(int op, bool a_first, int src) {
 }  // namespace
 
 
-// LDS per tree: node record (int), prefix sums E and difference array D
-// (int, Lmax + 1 entries each, rounded up) and subtree size (short).
-__host__ __device__ constexpr int plan_lpad(int Lmax) { return (Lmax + kWave) / kWave * kWave; }
-__host__ __device__ constexpr size_t plan_lds_bytes(int Lmax) {
-  // + one byte per program word: spill slot + 1 to set on the load at that word, or 0
-  return (size_t)plan_lpad(Lmax) * (3 * sizeof(int) + sizeof(short)) + (size_t)(prog_stride(Lmax) + 3) / 4 * 4;
-}
-
 // packed fields of the prefix sums E: code size (bits 0..15), function nodes (16..31)
 // and of the ancestor sums D: code start (0..11), spill base (12..15), record shift (16..)
 constexpr int kStartBits = 12;
+
+// Heavy child of function node h (its larger function child, the one its code
+// evaluates first, ties: the first child; or its only function child), or -1;
+// `light` receives the other function child of a node with two, or -1.
+__device__ int heavy_child(const int* s_rec, const short* s_sz, int h, int& light) {
+  light = -1;
+  const int c1 = h + 1;
+  const bool f1 = rec_kind(s_rec[c1]) == kTypeFunc;
+  if (rec_arity(s_rec[h]) == 1) return f1 ? c1 : -1;
+  const int c2 = c1 + s_sz[c1];
+  const bool f2 = rec_kind(s_rec[c2]) == kTypeFunc;
+  if (f1 && f2) {
+    if (s_sz[c1] >= s_sz[c2]) {
+      light = c2;
+      return c1;
+    }
+    light = c1;
+    return c2;
+  }
+  return f1 ? c1 : (f2 ? c2 : -1);
+}
+
+// Values (each K points of a lane) the heavy-path sweep holds at once: at the
+// start of each path, the captures of the path's function children plus the
+// adjoint of every waiting light child. Along a path the count only falls (a
+// record pops its children's captures before it parks its light child), so
+// the path starts give the maximum. Sequential; one lane.
+__device__ int path_need(const int* s_rec, const short* s_sz, int* stk) {
+  int sp = 0, need = 0;
+  stk[sp++] = 0;
+  while (sp > 0) {
+    const int F = stk[--sp];
+    int caps = 0, lt;
+    for (int h = F; h >= 0;) {
+      const int hv = heavy_child(s_rec, s_sz, h, lt);
+      caps += (hv >= 0) + (lt >= 0);
+      h = hv;
+    }
+    need = max(need, sp + caps);
+    for (int h = F; h >= 0;) {
+      const int hv = heavy_child(s_rec, s_sz, h, lt);
+      if (lt >= 0) stk[sp++] = lt;
+      h = hv;
+    }
+    need = max(need, sp);
+  }
+  return need;
+}
+
+// Heavy-path adjoint records in processing order (tgp_isa.h). Sequential; one lane.
+__device__ void emit_path_records(const int* s_rec, const short* s_sz, const int* s_D, const int* s_E,
+                                  const float* vrow, int* stk, uint32_t* recs) {
+  int sp = 0, q = 0;
+  stk[sp++] = 0;
+  while (sp > 0) {
+    const int F = stk[--sp];
+    int lt;
+    for (int h = F; h >= 0;) {
+      const int hv = heavy_child(s_rec, s_sz, h, lt);
+      const int r = s_rec[h];
+      const int ar = rec_arity(r);
+      const int c1 = h + 1;
+      const int ch[2] = {c1, ar == 2 ? c1 + s_sz[c1] : -1};
+      uint32_t pay[2] = {0, 0}, node[2] = {0, 0};
+      int kinds[2] = {kKindConst, kKindConst}, vars[2] = {0, 0};
+      for (int k = 0; k < ar; ++k) {
+        const int c = ch[k];
+        const int rc = s_rec[c];
+        if (c == hv) {
+          kinds[k] = kPathHeavy;
+        } else if (c == lt) {
+          kinds[k] = kPathLight;
+          const int start = s_D[c] & ((1 << kStartBits) - 1);
+          const int clen = (s_E[c + s_sz[c]] - s_E[c]) & 0xffff;
+          const int ld = (s_D[c] >> kStartBits) & 15;
+          pay[k] = (uint32_t)(start | (clen << 12) | (ld << 24));
+        } else if (rec_kind(rc) == kTypeVar) {
+          kinds[k] = kKindVar;
+          vars[k] = rec_var(rc);
+        } else {
+          kinds[k] = kKindConst;
+          pay[k] = __float_as_uint(vrow[c]);
+          node[k] = (uint32_t)c;
+        }
+      }
+      const uint32_t w0 = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) | (kinds[0] << 7) |
+                                     (kinds[1] << 9) | (vars[0] << 11) | (vars[1] << 15) |
+                                     ((hv < 0 ? 1 : 0) << 19) | ((lt >= 0 ? 1 : 0) << 20) |
+                                     ((hv >= 0 ? 1 : 0) << 21)) |
+                          (node[0] << 22);
+      *(uint4*)(recs + (int64_t)q * kPathWords) = make_uint4(w0, pay[0], pay[1], node[1]);
+      ++q;
+      h = hv;
+    }
+    // light children wait in path order, so the deepest one is taken first
+    for (int h = F; h >= 0;) {
+      const int hv = heavy_child(s_rec, s_sz, h, lt);
+      if (lt >= 0) stk[sp++] = lt;
+      h = hv;
+    }
+  }
+}
+
+// LDS per tree: node record (int), prefix sums E and difference array D
+// (int, Lmax + 1 entries each, rounded up), subtree size (short), one byte
+// per program word and, for gradient calls, a stack of nodes for the
+// heavy-path walk (int).
+__host__ __device__ constexpr int plan_lpad(int Lmax) { return (Lmax + kWave) / kWave * kWave; }
+__host__ __device__ constexpr size_t plan_lds_bytes(int Lmax, bool adj) {
+  // + one byte per program word: spill slot + 1 to set on the load at that word, or 0
+  return (size_t)plan_lpad(Lmax) * (3 * sizeof(int) + sizeof(short)) + (size_t)(prog_stride(Lmax) + 3) / 4 * 4 +
+         (adj ? (size_t)plan_lpad(Lmax) * sizeof(int) : 0);
+}
+
 
 // NCH = node chunks of 64 held in registers while the row is decoded (Lmax <= 64 NCH)
 template <int NCH>
@@ -177,6 +286,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   int* s_D = s_E + Lp;    // difference array, then ancestor sums (start | base << 12 | shift << 16)
   short* s_sz = (short*)(s_D + Lp);
   unsigned char* s_pre = (unsigned char*)(s_sz + Lp);  // per program word: spill slot + 1, or 0
+  int* s_stk = (int*)(s_pre + (prog_stride(a.Lmax) + 3) / 4 * 4);  // heavy-path walk: stack of path heads
 
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
@@ -212,7 +322,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
   if (!(is_intf(s0) && s0 >= 1.0f && s0 <= (float)Lmax)) status = 1;
   else len = (int)s0;
 
-  int n_const = 0, n_modi = 0, max_stack = 0, need0 = 0, prog_len = 0, n_int = 0;
+  int n_const = 0, n_modi = 0, max_stack = 0, need0 = 0, prog_len = 0, n_int = 0, adj_fmt = kAdjFmtRecompute;
 
   if (status == 0) {
     const int scan_end = a.check_tail ? Lmax : len;
@@ -377,6 +487,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int v = csF + (1 << kStartBits);
       atomicAdd(&s_D[S], v);
       atomicAdd(&s_D[S + zS], -v);
+      if (a.adj) atomicOr(&s_rec[S], kRecLight);
       if (a.adj && z2 < z1) {
         const int n1 = (s_E[c2] - s_E[c1]) >> 16, n2 = (s_E[c2 + z2] - s_E[c2]) >> 16;
         atomicAdd(&s_D[c2], -(n1 << 16));
@@ -445,6 +556,10 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (rec_kind(r) != kTypeFunc) continue;
       const int sb = s_D[i];
       const int st = sb & ((1 << kStartBits) - 1), bs = (sb >> kStartBits) & 15;
+      // gradient calls: the node's last word captures its value for its parent's path (the
+      // parent's light depth: this node's, less one when this node is a light child)
+      const int capl = (a.adj && i > 0) ? bs - ((r & kRecLight) ? 1 : 0) : -1;
+      auto cap = [capl](uint32_t w) { return capl >= 0 ? with_capture(w, capl) : w; };
       const int cs = (s_E[i + s_sz[i]] - s_E[i]) & 0xffff;
       const int oc = own_code(r);
       const int pos = st + cs - oc;  // first own instruction
@@ -462,8 +577,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           leaf_src(r1, vrow[c1], src, pay);
           wd = load_word(src, unary_act(op, mo), s_pre[pos]);
         }
-        put(prog, a.pstride, pos, wd, pay);
-        if (mo >= 0) put(prog, a.pstride, pos + 1, mkword(kACC, mo), 0.0f);
+        put(prog, a.pstride, pos, mo >= 0 ? wd : cap(wd), pay);
+        if (mo >= 0) put(prog, a.pstride, pos + 1, cap(mkword(kACC, mo)), 0.0f);
         continue;
       }
       const int z1 = s_sz[c1];
@@ -481,7 +596,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         a_first = v1;
         uint32_t wd = with_preload(mkword(fused_case(op, a_first, src), aux), pv);
         if (s_pre[pos]) wd = with_spill(wd, s_pre[pos] - 1);
-        put(prog, a.pstride, pos, wd, pay);
+        put(prog, a.pstride, pos, cap(wd), pay);
         continue;
       } else if (l1 && l2) {
         int s1; float p1;
@@ -505,9 +620,9 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (mo >= 0) {
         put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
         put(prog, a.pstride, pos + 1, mkword(kMB + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
-        put(prog, a.pstride, pos + 2, mkword(kACC, mo), 0.0f);
+        put(prog, a.pstride, pos + 2, cap(mkword(kACC, mo)), 0.0f);
       } else {
-        put(prog, a.pstride, pos, mkword(fused_case(op, a_first, src), aux), pay);
+        put(prog, a.pstride, pos, cap(mkword(fused_case(op, a_first, src), aux)), pay);
       }
     }
     if (lane == 0) {
@@ -516,13 +631,24 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     }
 
     // ---- pass 7: adjoint records (gradient calls only) ----
-    // Record q of a function node: its position in a pre-order walk that
-    // visits the smaller child first = (function nodes before it in the
-    // array) + (its ancestors' shifts). A record whose node is the
-    // later-visited child of a node with two function children takes its
-    // adjoint from the pending stack ("pop"); that parent pushes it.
-    if (a.adj) {
-      uint32_t* recs = a.adj + t * (int64_t)Lmax * kAdjWords;
+    // Heavy-path format when the sweep's live values fit the adjoint kernel's
+    // budget (adj_cap), else the recompute format.
+    // Recompute format: record q of a function node is its position in a
+    // pre-order walk that visits the smaller child first = (function nodes
+    // before it in the array) + (its ancestors' shifts). A record whose node
+    // is the later-visited child of a node with two function children takes
+    // its adjoint from the pending stack ("pop"); that parent pushes it.
+    uint32_t* recs = a.adj ? a.adj + t * (int64_t)Lmax * kAdjWords : nullptr;
+    if (a.adj && a.adj_cap > 0) {
+      int need = 0;
+      if (lane == 0 && rec_kind(root) == kTypeFunc) need = path_need(s_rec, s_sz, s_stk);
+      need = __shfl(need, 0, kWave);
+      if (need <= a.adj_cap) adj_fmt = kAdjFmtPath;
+    }
+    if (adj_fmt == kAdjFmtPath) {
+      // a single-leaf tree has no records
+      if (lane == 0 && rec_kind(root) == kTypeFunc) emit_path_records(s_rec, s_sz, s_D, s_E, vrow, s_stk, recs);
+    } else if (a.adj) {
       for (int ch = 0; ch < nch; ++ch) {
         const int i = ch * kWave + lane;
         if (i >= len) continue;
@@ -579,6 +705,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
 
   if (status != 0) {
     len = 0; n_const = 0; n_modi = 0; max_stack = 0; need0 = 0; prog_len = 0; n_int = 0;
+    adj_fmt = kAdjFmtRecompute;
   }
   if (lane == 0) {
     const int bucket = len <= 1 ? 0 : 32 - __clz(len - 1);
@@ -591,8 +718,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     info[kInfoProgLen] = prog_len;
     info[kInfoNeed] = need0;
     info[kInfoNInternal] = n_int;
+    info[kInfoAdjFmt] = adj_fmt;
     info[kInfoHdr] = (int32_t)((uint32_t)t | (status != 0 ? kHdrInvalid : 0u) | (n_modi > 0 ? kHdrModi : 0u));
-    a.acc[t] = 0.0;
     if (a.out_status) a.out_status[t] = status;
     if (a.out_info) {
       int32_t* o = a.out_info + t * 6;
@@ -653,7 +780,7 @@ __global__ __launch_bounds__(kOrderBlock) void order_kernel(OrderArgs a) {
 hipError_t launch_plan(const PlanArgs& a, hipStream_t s) {
   if (a.P <= 0) return hipSuccess;
   const dim3 grid((unsigned)a.P), block(64);
-  const size_t lds = plan_lds_bytes(a.Lmax);
+  const size_t lds = plan_lds_bytes(a.Lmax, a.adj != nullptr);
   if (a.Lmax <= 64) plan_kernel<1><<<grid, block, lds, s>>>(a);
   else if (a.Lmax <= 128) plan_kernel<2><<<grid, block, lds, s>>>(a);
   else if (a.Lmax <= 256) plan_kernel<4><<<grid, block, lds, s>>>(a);

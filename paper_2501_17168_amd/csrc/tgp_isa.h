@@ -64,6 +64,12 @@ constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 //   25      pre-load flag, 26..29 variable: after the spill and before the
 //           case, A = x[variable] (a binary node over two leaves is then
 //           one word)
+//   13      capture flag, with a 4-bit level in bits 14..15 (low) and
+//           30..31 (high): set on the last word of every non-root function
+//           node (after it, A holds the value the node hands to its parent);
+//           the level is the light depth of the node's parent (below). Only
+//           the adjoint's interpreter reads these bits: a run at level l
+//           pushes A on the capture stack after every word whose level is l.
 constexpr int kLD = 0;                    // A = src
 constexpr int kTLD = kLD + kNumSrc;       // T = src
 constexpr int kADD = kTLD + kNumSrc;      // A = A + src
@@ -83,6 +89,7 @@ constexpr int kNumCases = kEND + 1;
 
 constexpr int kCaseBits = 9, kSpillShift = 9, kSpillFlag = 1 << 12, kActShift = 16, kAuxShift = 22;
 constexpr int kAuxMask = 7, kPreLoadFlag = 1 << 25, kPreLoadShift = 26;
+constexpr uint32_t kCapFlag = 1u << 13;
 // actions (bits 16..21 of a word)
 constexpr int kActModi = 8, kActUn = 16, kActStop = 32;
 
@@ -96,12 +103,18 @@ __host__ __device__ constexpr int word_case(uint32_t w) { return (int)(w & ((1u 
 __host__ __device__ constexpr uint32_t with_preload(uint32_t w, int var) {
   return w | (uint32_t)kPreLoadFlag | ((uint32_t)var << kPreLoadShift);
 }
+__host__ __device__ constexpr uint32_t with_capture(uint32_t w, int level) {
+  return w | kCapFlag | ((uint32_t)(level & 3) << 14) | ((uint32_t)(level >> 2) << 30);
+}
+__host__ __device__ constexpr int capture_level(uint32_t w) { return (int)(((w >> 14) & 3u) | ((w >> 28) & 12u)); }
 
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]
+// kInfoAdjFmt: the adjoint-record format written for the tree (gradient calls):
+// kAdjFmtRecompute or kAdjFmtPath, below.
 constexpr int kInfoStatus = 0, kInfoLen = 1, kInfoMaxStack = 2, kInfoNConst = 3, kInfoNModi = 4,
               kInfoBucket = 5, kInfoProgLen = 6, kInfoNeed = 7, kInfoNInternal = 8, kInfoHdr = 9,
-              kInfoStride = 10;
+              kInfoAdjFmt = 10, kInfoStride = 11;
 
 // tree header word (info[kInfoHdr]) and persistent order entries: tree index in the low 30 bits
 constexpr uint32_t kHdrInvalid = 1u << 31, kHdrModi = 1u << 30, kHdrTree = (1u << 30) - 1;
@@ -124,6 +137,33 @@ constexpr uint32_t kHdrInvalid = 1u << 31, kHdrModi = 1u << 30, kHdrTree = (1u <
 // child's adjoint goes to the pending stack.
 constexpr int kAdjWords = 8;
 constexpr int kKindFunc = 0, kKindVar = 1, kKindConst = 2, kKindNone = 3;
+
+// ---- adjoint records, heavy-path format ----
+// The heavy child of a function node is its larger function child (the one
+// its code evaluates first; ties: the first child), or its only function
+// child; the other function child of a node with two is light. A node's
+// light depth counts the light edges from the root to it. Following heavy
+// children from a node F (F = the root or a light child) gives F's path.
+// Running F's code once at level light_depth(F) captures, in code order, the
+// values of the function children of every node on F's path: deepest first,
+// the heavy child before the light one, so the node at the top of the path
+// finds its children's values at the top of the capture stack.
+// Records, one per function node, come in processing order: F's path top
+// down; then, deepest light child first, each light child's own path and
+// what hangs below it (the light children wait on a pending stack).
+// A record is 4 words (kPathWords; the records of a tree are kPathWords apart):
+//   w0 = op | arity << 4 | modi << 6 | kind_a << 7 | kind_b << 9 | var_a << 11
+//        | var_b << 15 | end_of_path << 19 | has_light << 20 | has_heavy << 21
+//        | (node index of a constant child a) << 22
+//   w1 = child a's payload: a constant's bits, or for a light child
+//        code start | code length << 12 | light depth << 24
+//   w2 = child b's payload, likewise
+//   w3 = node index of a constant child b
+// kind: kPathHeavy, kKindVar, kKindConst or kPathLight (kind_b is unused for
+// a unary node).
+constexpr int kPathHeavy = 0, kPathLight = 3, kPathWords = 4;
+// per-tree record format
+constexpr int kAdjFmtRecompute = 0, kAdjFmtPath = 1;
 
 // program capacity per tree, in instructions (bound: 2*len + #unary nodes + 2 <= 3*Lmax + 2)
 __host__ __device__ constexpr int64_t prog_stride(int Lmax) { return ((3 * (int64_t)Lmax + 2) + 7) / 8 * 8; }

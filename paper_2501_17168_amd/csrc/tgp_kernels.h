@@ -21,8 +21,8 @@ struct PlanArgs {
   int32_t* info;        // [P][kInfoStride]
   uint2* prog;          // [P][prog_stride(Lmax)]
   int64_t pstride;
-  double* acc;          // [P], zeroed by the plan
   uint32_t* adj;        // optional [P][Lmax][kAdjWords] adjoint records
+  int32_t adj_cap;      // values the heavy-path sweep may hold per wave (0: recompute format only)
   int32_t* out_info;    // optional [P][6]
   int32_t* out_status;  // optional [P]
   int32_t* zero;        // optional counters the plan zeroes (their readers run after it)
@@ -59,7 +59,7 @@ struct EvalArgs {
   const int32_t* info;
   const uint2* prog;
   int64_t pstride;
-  double* acc;          // [P]
+  double* part;         // fitness partials [ntiles][P]: part[tile * P + t], one per (tree, tile)
   float* pred;          // optional [P][n_out][ldp]
   int64_t ldp;
   int64_t P;
@@ -86,7 +86,7 @@ struct AdjArgs {
   int64_t pstride;
   const uint32_t* adj;  // adjoint records [P][Lmax][kAdjWords]
   int32_t Lmax;
-  double* acc;          // [P]
+  double* part;         // fitness partials [ntiles][P], as for the forward kernel
   const float* grad_mse;  // optional [P]
   float* grad_value;    // optional [P][gv_stride], zeroed beforehand
   int64_t gv_stride;
@@ -95,12 +95,18 @@ struct AdjArgs {
   int32_t ntiles;
   int32_t ngroups;
   int32_t tpu;
-  int32_t pend_slots;   // pending-adjoint stack entries per wave
+  int32_t pend_slots;   // pending-adjoint stack entries per wave (recompute sweep)
+  int32_t cap;          // LDS values per wave of the heavy-path sweep (0: not launched)
 };
 
+// Fitness from the per-(tree, tile) partials, summed in a fixed order (tiles
+// split into `segs` interleaved segments summed in order, segments added in
+// order), so repeated calls give bitwise identical results.
 struct FinalArgs {
   const int32_t* info;
-  const double* acc;
+  const double* part;   // [ntiles][P]; read only when mse is requested
+  int32_t ntiles;
+  int32_t segs;         // 1..16 segments per tree (a power of two)
   int64_t P;
   double inv_D;
   float* mse;
@@ -112,6 +118,8 @@ hipError_t launch_plan(const PlanArgs& a, hipStream_t s);
 hipError_t launch_order(const OrderArgs& a, hipStream_t s);
 hipError_t launch_eval(const EvalArgs& a, int K, int VM, int NO, bool pred, int block_waves,
                        int64_t grid, hipStream_t s);
+// waves of this evaluation-kernel instantiation resident on one CU at once
+int eval_resident_waves(int K, int VM, int NO, bool pred, int block_waves);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, int K, int VM, int block_waves, int64_t grid, hipStream_t s);
 hipError_t launch_zero_f32(float* p, int64_t rows, int64_t cols, int64_t ld, hipStream_t s);

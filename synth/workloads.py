@@ -49,6 +49,18 @@ WORKLOADS = {
              "8 vars N(0,1), 65,536 points, hidden full(4) tree + N(0,0.01)",
         P=50_000, Lmax=256, V=8, D=65_536, funcs="F11", shape=("ramped", 2, 8), x=("normal", 0.0, 1.0),
         target=("full", 4), sigma=0.01, n_out=1, seed=4, n_sample=100, const_cap=32),
+    # the same shapes with only the cheap arithmetic operators: the interpreter's dispatch cost is
+    # then most of the work per node
+    "hybrid-arith": dict(
+        desc="10,000 trees, Lmax 256, ramped half-and-half depth 2..8, {+,-,*,pdiv}, 2 vars U(-4,4), "
+             "2,000 points, hidden full(4) tree + N(0,0.01)",
+        P=10_000, Lmax=256, V=2, D=2_000, funcs="F4", shape=("ramped", 2, 8), x=("uniform", -4.0, 4.0),
+        target=("full", 4), sigma=0.01, n_out=1, seed=11, n_sample=None),
+    "batched-arith": dict(
+        desc="200,000 trees, Lmax 1024, exact lengths log-uniform in [3,1024], {+,-,*,pdiv}, 4 vars "
+             "U(-2,2), 4,096 points, 3 outputs (three hidden full(4) trees + N(0,0.01)), 10% Modi trees",
+        P=200_000, Lmax=1024, V=4, D=4_096, funcs="F4", shape=("loguniform", 3, 1024), x=("uniform", -2.0, 2.0),
+        target=("full", 4), sigma=0.01, n_out=3, seed=13, n_sample=2_000, modi_frac=0.1),
     "classify": dict(
         desc="classification, Wine-shaped: 5,000 multi-output trees (Modi outputs for 3 classes), ramped "
              "half-and-half depth 2..6, 11 ops, 13 vars N(0,1), 178 points, labels = argmax of 3 random "

@@ -238,14 +238,31 @@ def test_edge_shapes(K):
             compare_fitness(got, ref, label=f"D={D} mode={mode}")
 
 
-def test_repeat_runs_identical():
+# every schedule, the dynamic persistent queue included: per-(tree, tile) partials summed in a fixed
+# order make the fitness independent of which wave finished first
+REPEAT_SCHEDULES = [None, dict(mode=1, points_per_lane=4, block_waves=4),
+                    dict(mode=2, points_per_lane=8, block_waves=4, trees_per_unit=16),
+                    dict(mode=3, points_per_lane=8, block_waves=1, trees_per_unit=1),
+                    dict(mode=3, points_per_lane=4, block_waves=4, trees_per_unit=2, flags=2)]
+
+
+@pytest.mark.parametrize("sched", REPEAT_SCHEDULES, ids=["default", "tree", "point", "persistent", "static"])
+def test_repeat_runs_identical(sched):
     w, Y = work("hybrid", **SMALL["hybrid"])
     pop, X, Yd = to_dev(w, Y)
-    a = device_fit(pop, X, Yd, 1)
-    b = device_fit(pop, X, Yd, 1)
-    same = (a == b) | (np.isnan(a) & np.isnan(b))
-    assert same.mean() > 0.999
-    np.testing.assert_allclose(a, b, rtol=1e-6)
+    c = tgp.cfg(sched) if sched else None
+    runs = [device_fit(pop, X, Yd, 1, config=c) for _ in range(4)]
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r.view(np.uint32), runs[0].view(np.uint32))
+
+
+def test_repeat_runs_identical_multi_output():
+    w, Y = work("batched", **SMALL["batched"])
+    pop, X, Yd = to_dev(w, Y)
+    c = tgp.cfg(mode=3, points_per_lane=8, block_waves=1, trees_per_unit=1)
+    runs = [device_fit(pop, X, Yd, w.n_out, config=c) for _ in range(3)]
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r.view(np.uint32), runs[0].view(np.uint32))
 
 
 def test_strided_rows_and_views():

@@ -57,13 +57,27 @@ def test_grad_matches_oracle(name, kw, k):
     mse, gv, gx = tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, points_per_lane=k))
     torch.cuda.synchronize()
     ref = grad_ref(name, w, Y)
-    rep_f = compare_fitness(mse.cpu().numpy(), FitnessRef(w.type, w.value, w.size, w.X, Y), label=f"{name} fitness")
+    fref = FitnessRef(w.type, w.value, w.size, w.X, Y)
+    rep_f = compare_fitness(mse.cpu().numpy(), fref, label=f"{name} fitness")
     rep_v = compare_grad_value(gv.cpu().numpy(), ref, label=name)
     rep_x = compare_grad_x(gx.cpu().numpy(), ref, label=name)
     print(f"{name} K={k}: fitness {rep_f}\n  grad_value {rep_v}\n  grad_X {rep_x}", flush=True)
-    # the envelopes are narrow enough to mean something on most components
+    # the envelopes are narrow enough to mean something on most constant gradients
     assert rep_v["tight"] >= 0.25 * rep_v["n"], rep_v
-    assert rep_x["tight"] >= 0.25 * rep_x["n"], rep_x
+    # grad_X sums over every tree, so one tree with a wide envelope (tan near its poles, a
+    # near-singular quotient) widens the sum at every point. The same call on the sub-population
+    # of trees whose fitness envelope is within 1e-5 checks the X gradient of the well-determined
+    # trees at the 1e-3 bar.
+    tol = np.maximum(1e-5 * np.abs(fref.m64), 1e-6)
+    with np.errstate(invalid="ignore"):
+        good = np.isfinite(fref.m64) & ~fref.nan & (fref.lo >= fref.m64 - tol) & (fref.hi <= fref.m64 + tol)
+    sub = [np.ascontiguousarray(a[good]) for a in (w.type, w.value, w.size)]
+    pop_sub = tgp.Population(*(torch.from_numpy(a).to(DEV) for a in sub))
+    _, _, gxs = tgp.eval_mse_grad(pop_sub, X, Yd, config=tgp.cfg(mode=2, points_per_lane=k))
+    torch.cuda.synchronize()
+    rep_xs = compare_grad_x(gxs.cpu().numpy(), GradRef(*sub, w.X, Y), label=name + " well-determined")
+    print(f"  grad_X over the {int(good.sum())} well-determined trees {rep_xs}", flush=True)
+    assert rep_xs["tight"] >= 0.25 * rep_xs["n"], rep_xs
 
 
 def test_grad_vs_finite_differences():
@@ -209,3 +223,47 @@ def test_grad_launch_shapes_agree(cfg):
     compare_fitness(mse, FitnessRef(w.type, w.value, w.size, w.X, Y), label=f"{cfg} fitness")
     compare_grad_value(gv, ref, label=str(cfg))
     compare_grad_x(gx, ref, label=str(cfg))
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_path_and_recompute_sweeps_agree(k):
+    """The heavy-path sweep and the recompute sweep (TGP_FLAG_ADJ_RECOMPUTE) on the same trees:
+    the fitness comes from the same forward run and is bitwise equal; the gradients differ only
+    in the order of float32 sums, and both lie inside the oracle's envelopes."""
+    w, Y = work("hybrid", P=250, D=2000)
+    pop = dev_pop(w)
+    X = torch.from_numpy(w.X).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
+    ref = grad_ref("hybrid", w, Y)
+    res = {}
+    for name, flags in (("path", 0), ("recompute", 4)):
+        got = tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, points_per_lane=k, flags=flags))
+        torch.cuda.synchronize()
+        res[name] = [t.cpu().numpy() for t in got]
+        compare_grad_value(res[name][1], ref, label=name)
+        compare_grad_x(res[name][2], ref, label=name)
+    np.testing.assert_array_equal(res["path"][0].view(np.uint32), res["recompute"][0].view(np.uint32))
+
+
+def test_deep_trees_mix_both_sweeps():
+    """Single-output trees of the batched recipe (exact lengths up to 1024, Lmax 1024): the deep
+    ones need more than the heavy-path sweep's LDS budget and go to the recompute sweep, the rest
+    to the heavy-path sweep, in one call. Fitness and gradients inside the envelopes."""
+    wb = synth.workload("batched", P=160, D=700)
+    plain = np.setdiff1d(np.arange(wb.P), wb.meta["modi_trees"])
+    sub = [np.ascontiguousarray(a[plain]) for a in (wb.type, wb.value, wb.size)]
+    # target: the first hidden tree plus its noise row
+    hp = O.predict(*(np.ascontiguousarray(h[:1]) for h in wb.hidden), wb.X, 1)[0, 0]
+    Y = (hp + wb.noise[0].astype(np.float64)).astype(np.float32)[None, :]
+    # heavy-path values the sweep holds per tree (the plan's budget is 16)
+    lengths = sub[2][:, 0]
+    assert lengths.max() > 600
+    pop = tgp.Population(*(torch.from_numpy(a).to(DEV) for a in sub))
+    X = torch.from_numpy(wb.X).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
+    mse, gv, gx = (t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, points_per_lane=2)))
+    compare_fitness(mse, FitnessRef(*sub, wb.X, Y), label="deep fitness")
+    ref = GradRef(*sub, wb.X, Y)
+    rep_v = compare_grad_value(gv, ref, label="deep")
+    rep_x = compare_grad_x(gx, ref, label="deep")
+    print(f"deep trees: grad_value {rep_v}\n  grad_X {rep_x}", flush=True)
