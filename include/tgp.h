@@ -58,7 +58,9 @@ enum {
   TGP_E_SHAPE = -2,        /* inconsistent sizes or strides                       */
   TGP_E_WORKSPACE = -4,    /* workspace null, misaligned or smaller than needed   */
   TGP_E_UNSUPPORTED = -5,  /* sizes beyond the limits listed above                */
-  TGP_E_HIP = -6           /* a HIP runtime call or kernel launch failed          */
+  TGP_E_HIP = -6,          /* a HIP runtime call or kernel launch failed          */
+  TGP_E_TOO_LARGE = -7     /* tgp_eval_mse_noalloc: the call needs more scratch than
+                              the static buffer holds                             */
 };
 
 /* Per-tree status codes written to tree_status[t] (the smallest applicable):
@@ -139,6 +141,24 @@ tgp_status tgp_plan(const tgp_pop* pop, int32_t V, int32_t n_out, const tgp_cfg*
 tgp_status tgp_eval_mse(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
                         float* mse, int32_t* tree_status, void* ws, size_t ws_bytes,
                         hipStream_t stream);
+
+/* tgp_eval_mse for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and launches as tgp_eval_mse, but no workspace:
+ * the scratch comes from a static device array of TGP_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) that each device running the library holds until the process
+ * ends. The call allocates nothing (its first call on a device looks up the
+ * array's address once); the caller still passes the inputs and outputs.
+ * A call whose workspace would exceed the array returns TGP_E_TOO_LARGE and
+ * enqueues nothing: tgp_workspace_bytes(pop, data, 1, 0) must be at most
+ * TGP_NOALLOC_SCRATCH_BYTES (for example up to 5,298 trees of Lmax 256 on
+ * 2,000 points; 2,000 such trees need 12.7 MB). All calls on one device share its array, which
+ * keeps the last call's contents (nothing in it needs to start at zero:
+ * every call writes what it reads), so calls that overlap in time on one
+ * device, on any streams, race and must not be issued. */
+#define TGP_NOALLOC_SCRATCH_BYTES (32u << 20)
+tgp_status tgp_eval_mse_noalloc(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
+                                float* mse, int32_t* tree_status, hipStream_t stream);
 
 /* Multi-output evaluation (§IV-C). With data->Y: mse[t] = sum over the
  * n_out outputs of the mean squared error (mse may be NULL to skip).

@@ -13,6 +13,7 @@ from ._lib import (  # noqa: F401
     status_str, LIB_PATH, XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR,
 )
 from .api import (  # noqa: F401
-    Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_multi_output, eval_accuracy, eval_mse_grad, autotune,
+    Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_mse_noalloc, eval_multi_output, eval_accuracy,
+    eval_mse_grad, autotune,
     subtree_exchange, crossover, mutation, generate, TreeMSE,
 )

@@ -17,6 +17,8 @@ TGP_E_SHAPE = -2
 TGP_E_WORKSPACE = -4
 TGP_E_UNSUPPORTED = -5
 TGP_E_HIP = -6
+TGP_E_TOO_LARGE = -7
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT = 0, 1, 2, 3
 FLAG_NO_TAIL_CHECK = 1
@@ -24,7 +26,8 @@ FLAG_STATIC_ORDER = 2
 FLAG_ADJ_RECOMPUTE = 4
 
 # symbols the header declares; the CPU tests check that each one is exported
-EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_multi_output", "tgp_eval_accuracy",
+EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_mse_noalloc", "tgp_eval_multi_output",
+           "tgp_eval_accuracy",
            "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_generate", "tgp_status_str", "tgp_op_cost",
            "tgp_profile", "tgp_profile_read")
 
@@ -94,6 +97,8 @@ def load():
     lib.tgp_plan.restype = i32
     lib.tgp_eval_mse.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp, ctypes.c_size_t, vp]
     lib.tgp_eval_mse.restype = i32
+    lib.tgp_eval_mse_noalloc.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, vp]
+    lib.tgp_eval_mse_noalloc.restype = i32
     lib.tgp_eval_multi_output.argtypes = [P(TgpPop), P(TgpData), P(TgpCfg), vp, vp, ctypes.c_int64, vp, vp,
                                           ctypes.c_size_t, vp]
     lib.tgp_eval_multi_output.restype = i32

@@ -14,7 +14,8 @@ import torch
 from . import _lib
 from ._lib import TgpCfg, TgpData, TgpExchange, TgpGenCfg, TgpPop, check
 
-__all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_multi_output", "eval_accuracy",
+__all__ = ["Population", "Workspace", "cfg", "workspace_bytes", "plan", "eval_mse", "eval_mse_noalloc",
+           "eval_multi_output", "eval_accuracy",
            "eval_mse_grad", "autotune", "subtree_exchange", "crossover", "mutation", "generate", "TreeMSE"]
 
 
@@ -169,6 +170,21 @@ def eval_mse(pop, X, y, config=None, ws=None, out=None, tree_status=None, stream
     stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
     check(lib.tgp_eval_mse(ctypes.byref(p), ctypes.byref(d), _cfgp(config), ctypes.c_void_p(mse.data_ptr()), stp,
                            wp, wn, _stream(stream)), "tgp_eval_mse")
+    return mse
+
+
+def eval_mse_noalloc(pop, X, y, config=None, out=None, tree_status=None, stream=None):
+    """eval_mse through tgp_eval_mse_noalloc: the library's static scratch buffer replaces the
+    workspace, so the call allocates nothing on the device (pass `out`, and `tree_status` if
+    wanted, to allocate nothing here either). Calls on one device must not overlap in time.
+    Returns float32 [P]."""
+    lib = _lib.load()
+    d, _ = _data(X, y, 1)
+    p = pop.abi()
+    mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device) if out is None else out
+    stp = ctypes.c_void_p(tree_status.data_ptr()) if tree_status is not None else None
+    check(lib.tgp_eval_mse_noalloc(ctypes.byref(p), ctypes.byref(d), _cfgp(config), ctypes.c_void_p(mse.data_ptr()),
+                                   stp, _stream(stream)), "tgp_eval_mse_noalloc")
     return mse
 
 

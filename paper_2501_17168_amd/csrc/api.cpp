@@ -457,6 +457,7 @@ __attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) 
     case TGP_E_WORKSPACE: return "workspace missing, misaligned or too small";
     case TGP_E_UNSUPPORTED: return "unsupported size (Lmax > 1024, V > 16 or n_out > 4)";
     case TGP_E_HIP: return "HIP runtime error";
+    case TGP_E_TOO_LARGE: return "the call needs more scratch than the static buffer of tgp_eval_mse_noalloc holds";
     default: return "unknown status";
   }
 }

@@ -198,3 +198,29 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def call_noalloc(p, d, mse=FAKE):
+    lib = tgp.load()
+    return lib.tgp_eval_mse_noalloc(ctypes.byref(p) if p else None, ctypes.byref(d) if d else None, None,
+                                    ctypes.c_void_p(mse) if mse else None, None, None)
+
+
+def test_eval_mse_noalloc_host_checks():
+    """The allocation-free call rejects what tgp_eval_mse rejects, with the same codes, and a
+    call whose workspace would not fit its static scratch buffer with TGP_E_TOO_LARGE; all before
+    any device work."""
+    assert call_noalloc(None, data()) == _lib.TGP_E_ARG
+    assert call_noalloc(pop(), None) == _lib.TGP_E_ARG
+    assert call_noalloc(pop(), data(), mse=0) == _lib.TGP_E_ARG
+    assert call_noalloc(pop(Lmax=2048), data()) == _lib.TGP_E_UNSUPPORTED
+    assert call_noalloc(pop(stride=10), data()) == _lib.TGP_E_SHAPE
+    assert call_noalloc(pop(), data(V=17)) == _lib.TGP_E_UNSUPPORTED
+    assert call_noalloc(pop(), data(n_out=2)) == _lib.TGP_E_SHAPE
+    assert call_noalloc(pop(), data(Y=0)) == _lib.TGP_E_ARG
+    # the largest population of Lmax 256 on 2,000 points that fits, and one tree more
+    fits = max(P for P in range(1, 6000, 1) if ws_bytes(pop(P, 256), data(D=2000)) <= _lib.NOALLOC_SCRATCH_BYTES)
+    assert fits > 2000
+    assert call_noalloc(pop(fits + 1, 256), data(D=2000)) == _lib.TGP_E_TOO_LARGE
+    assert call_noalloc(pop(200_000, 1024), data(V=4, D=4096)) == _lib.TGP_E_TOO_LARGE
+    assert "static buffer" in _lib.status_str(_lib.TGP_E_TOO_LARGE)
