@@ -38,7 +38,9 @@
  *   - `ws` is a caller-owned device workspace of at least
  *     tgp_workspace_bytes(...) bytes, 256-byte aligned. Its contents are
  *     scratch between calls; concurrent calls must not share one workspace.
- *   - Limits: 1 <= Lmax <= 1024, 1 <= V <= 16, 1 <= n_out <= 4, D >= 1.
+ *   - Limits: 1 <= Lmax <= 1024, 1 <= V <= 16, 1 <= n_out <= 12 (<= 4 for
+ *     gradients; populations of more than 4 outputs run at 4 points per lane),
+ *     D >= 1.
  */
 #ifndef TGP_H
 #define TGP_H
@@ -170,7 +172,7 @@ tgp_status tgp_eval_multi_output(const tgp_pop* pop, const tgp_data* data, const
                                  void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Classification fitness (the classification domain of §V-D; multi-output
- * trees of §IV-C): data->n_out = C classes (2..4), and row 0 of data->Y
+ * trees of §IV-C): data->n_out = C classes (2..12), and row 0 of data->Y
  * holds each point's class label (a float32 integer in [0, C); other values
  * never match). Tree t predicts class c(x) = the first index of the largest
  * of its C outputs, a NaN output counting below every number, and
@@ -196,9 +198,12 @@ tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp
  *   invalid trees).
  * grad_X: optional device float32 [V][ldx], overwritten with
  *   sum_t dL/dmse_t * dmse_t/dX.
- * n_out must be 1. mse: device float32 [P]. cfg: mode is ignored (the sweep
- * is point-major); points_per_lane 2 or 4 (anything else: 4), block_waves
- * and trees_per_unit as for the forward calls. */
+ * data->n_out outputs (1..4), as in tgp_eval_multi_output: mse[t] sums the
+ * outputs' mean squared errors, a Modi node for output o passes
+ * dL/dout_o * df/dchild to its children (§IV-C), and Y must hold n_out rows.
+ * mse: device float32 [P]. cfg: mode is ignored (the sweep is point-major);
+ * points_per_lane 2 or 4 (anything else: 4 for one output, 2 for several),
+ * block_waves and trees_per_unit as for the forward calls. */
 tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
                              const float* grad_mse, float* mse, float* grad_value,
                              float* grad_X, int32_t* tree_status, void* ws, size_t ws_bytes,
@@ -209,7 +214,7 @@ tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp
  * it in *out. Synchronises the stream; not capturable. With want_grad the
  * gradient call is tuned instead (its points per lane, 2 or 4, workgroup
  * shape and trees per unit;
- * n_out must be 1, and the workspace sized with want_grad), and later
+ * the workspace sized with want_grad), and later
  * tgp_eval_mse_grad calls on this shape with a NULL or AUTO cfg use it.
  * Allocates and frees temporary device buffers. */
 tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,

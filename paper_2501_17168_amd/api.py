@@ -235,14 +235,15 @@ def eval_multi_output(pop, X, Y=None, n_out=None, want_mse=True, want_pred=False
 
 def eval_mse_grad(pop, X, y, grad_mse=None, want_grad_value=True, want_grad_x=True, config=None, ws=None,
                   tree_status=None, stream=None):
-    """Fitness and gradients. Returns (mse [P], grad_value [P][Lmax] or None, grad_X [V][D] or None)."""
+    """Fitness and gradients against y [D] or Y [n_out][D] (n_out 1..4: multi-output trees, fitness
+    summed over outputs). Returns (mse [P], grad_value [P][Lmax] or None, grad_X [V][D] or None)."""
     lib = _lib.load()
-    d, _ = _data(X, y, 1)
+    d, _ = _data(X, y)
     p = pop.abi()
     mse = torch.empty((pop.P,), dtype=torch.float32, device=X.device)
     gv = torch.empty((pop.P, pop.type.stride(0)), dtype=torch.float32, device=X.device) if want_grad_value else None
     gx = torch.empty((X.shape[0], d.ldx), dtype=torch.float32, device=X.device) if want_grad_x else None
-    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), 1, 1)
+    nbytes = lib.tgp_workspace_bytes(ctypes.byref(p), ctypes.byref(d), d.n_out, 1)
     if nbytes == 0:
         raise _lib.TgpError(_lib.TGP_E_UNSUPPORTED, "tgp_eval_mse_grad")
     wp, wn = _ws(ws, nbytes, X.device)
@@ -370,7 +371,8 @@ def generate(P, Lmax, V, funcs, method="ramped", depth_min=2, depth_max=6, seed=
 class TreeMSE(torch.autograd.Function):
     """Fitness of every tree as a differentiable function of the node values and X.
 
-    ``TreeMSE.apply(value, type, size, X, y)`` returns float32 [P]. Backward calls
+    ``TreeMSE.apply(value, type, size, X, y)`` returns float32 [P] (y [D], or Y [n_out][D] for
+    multi-output trees, whose fitness sums the outputs' mean squared errors). Backward calls
     tgp_eval_mse_grad with the incoming gradient as the per-tree weights and
     returns (grad_value, None, None, grad_X, None). grad_value is zero at
     every non-constant and padding position, so an optimizer step on ``value``
@@ -380,7 +382,10 @@ class TreeMSE(torch.autograd.Function):
     @staticmethod
     def forward(ctx, value, type, size, X, y):
         pop = Population(type, value, size)
-        mse = eval_mse(pop, X, y)
+        if y.dim() == 2 and y.shape[0] > 1:
+            mse, _ = eval_multi_output(pop, X, y)
+        else:
+            mse = eval_mse(pop, X, y)
         ctx.save_for_backward(value, type, size, X, y)
         return mse
 

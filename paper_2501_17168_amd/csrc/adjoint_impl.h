@@ -14,7 +14,7 @@
 //      to grad_value, a function child becomes the next record's adjoint or
 //      waits on the pending stack (at most log2(len) entries deep).
 // Nothing is stored per point beyond the current path's adjoints. A Modi
-// node (single output) hands gbar * df/dchild to its children and passes its
+// node for output o hands gbar_o * df/dchild to its children and passes its
 // own adjoint on to its rightmost child, whose value it forwards.
 //
 // Work units are point-major: each workgroup holds block_waves tiles and a
@@ -93,14 +93,14 @@ __device__ __forceinline__ void partials_own(int op, float a, float b, float v, 
   }
 }
 
-template <int K, int VM>
+template <int K, int VM, int NO>
 struct AdjState {
-  Regs<K, VM, 1> s;
+  Regs<K, VM, NO> s;
   float gx[VM][K];  // grad_X accumulators for this lane's points
 };
 
-template <int K, int VM>
-__device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, 1>& s, int64_t p0) {
+template <int K, int VM, int NO>
+__device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, NO>& s, int64_t p0) {
 #pragma unroll
   for (int v = 0; v < VM; ++v) {
 #pragma unroll
@@ -112,8 +112,8 @@ __device__ __forceinline__ void load_x_adj(const AdjArgs& a, Regs<K, VM, 1>& s, 
 }
 
 // value of a leaf child for this lane's K points
-template <int K, int VM>
-__device__ __forceinline__ void leaf_value(const Regs<K, VM, 1>& s, int kind, int var, uint32_t bits, float out[K]) {
+template <int K, int VM, int NO>
+__device__ __forceinline__ void leaf_value(const Regs<K, VM, NO>& s, int kind, int var, uint32_t bits, float out[K]) {
   if (kind == kKindConst) {
 #pragma unroll
     for (int j = 0; j < K; ++j) out[j] = __uint_as_float(bits);
@@ -128,8 +128,8 @@ __device__ __forceinline__ void leaf_value(const Regs<K, VM, 1>& s, int kind, in
 }
 
 // a leaf child receives its adjoint
-template <int K, int VM>
-__device__ __forceinline__ void leaf_adjoint(const AdjArgs& a, AdjState<K, VM>& st, int64_t t, int64_t p0,
+template <int K, int VM, int NO>
+__device__ __forceinline__ void leaf_adjoint(const AdjArgs& a, AdjState<K, VM, NO>& st, int64_t t, int64_t p0,
                                              int lane, int kind, int var, uint32_t node, const float adj[K]) {
   if (kind == kKindVar) {
 #pragma unroll
@@ -147,9 +147,43 @@ __device__ __forceinline__ void leaf_adjoint(const AdjArgs& a, AdjState<K, VM>& 
   }
 }
 
+// After a tree's forward run: the fitness partial of the tile (a float64 sum of the
+// float32 squared residuals over the points and outputs) and the output adjoints
+// gbar[o] = g_t * 2 (out_o - Y_o) / D. A tree without Modi nodes predicts
+// (root, 0, ..., 0); outputs at or beyond n_out, and points past D, get 0.
+template <int K, int VM, int NO>
+__device__ __forceinline__ double output_adjoints(const AdjArgs& a, const Regs<K, VM, NO>& s, bool modi, float gt,
+                                                  int64_t p0, float (&gbar)[NO][K]) {
+  double sse = 0.0;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t p = p0 + j * kWave;
+      gbar[o][j] = 0.0f;
+      if (o < a.n_out && p < a.D) {
+        const float out = modi ? s.O[o][j] : (o == 0 ? s.A[j] : 0.0f);
+        const float e = out - a.Y[(int64_t)o * a.ldy + p];
+        sse += (double)(e * e);
+        gbar[o][j] = gt * 2.0f * e * a.inv_D;
+      }
+    }
+  }
+  return sse;
+}
+
+// The output adjoint of Modi output mo (wave-uniform) at point slot j.
+template <int K, int NO>
+__device__ __forceinline__ float out_adjoint(const float (&gbar)[NO][K], int mo, int j) {
+  float v = gbar[0][j];
+#pragma unroll
+  for (int o = 1; o < NO; ++o) v = (mo == o) ? gbar[o][j] : v;
+  return v;
+}
+
 }  // namespace
 
-template <int K, int VM>
+template <int K, int VM, int NO>
 __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
   extern __shared__ float s_lds[];
   constexpr int kTile = K * kWave;
@@ -168,9 +202,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
   const int64_t t1 = min(a.P, t0 + a.tpu);
   const int64_t p0 = (int64_t)tile * kTile + lane;
 
-  AdjState<K, VM> st;
-  Regs<K, VM, 1>& s = st.s;
-  load_x_adj<K, VM>(a, s, p0);
+  AdjState<K, VM, NO> st;
+  Regs<K, VM, NO>& s = st.s;
+  load_x_adj<K, VM, NO>(a, s, p0);
 #pragma unroll
   for (int v = 0; v < VM; ++v)
 #pragma unroll
@@ -190,7 +224,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
     prog_ptr prog = (prog_ptr)(a.prog + t * a.pstride);
     rec_ptr recs = (rec_ptr)(a.adj + t * (int64_t)a.Lmax * kAdjWords);
 
-    float gbar[K], cur[K];
+    float gbar[NO][K], cur[K];
     int sp = 0;
     // Step q = -1 is the forward pass (the whole program but its END); step
     // q >= 0 is adjoint record q. Every interpreter run of the tree happens
@@ -209,7 +243,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           s.A[j] = 0.0f;
-          s.O[0][j] = 0.0f;
+#pragma unroll
+          for (int o = 0; o < NO; ++o) s.O[o][j] = 0.0f;
         }
         nrun = 1;
         rs0 = 0;
@@ -235,7 +270,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
             d0 = 0;
             nrun = 1;
           } else {
-            leaf_value<K, VM>(s, k1, v1, w2, va);
+            leaf_value<K, VM, NO>(s, k1, v1, w2, va);
           }
           if (ar == 2) {
             if (k2 == kKindFunc) {
@@ -250,7 +285,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
               }
               ++nrun;
             } else {
-              leaf_value<K, VM>(s, k2, v2, w4, vb);
+              leaf_value<K, VM, NO>(s, k2, v2, w4, vb);
             }
           }
         }
@@ -259,7 +294,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
       for (int r = 0; r < nrun; ++r) {
         const uint32_t rs = r == 0 ? rs0 : rs1, rl = r == 0 ? rl0 : rl1;
         const int dst = r == 0 ? d0 : d1;
-        run_program<K, VM, 1, true>(prog + rs, s, spill, (int)rl);
+        run_program<K, VM, NO, true>(prog + rs, s, spill, (int)rl);
         if (dst == 0) {
 #pragma unroll
           for (int j = 0; j < K; ++j) va[j] = s.A[j];
@@ -270,36 +305,24 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
       }
 
       if (q < 0) {
-        // ---- forward: output, fitness, output adjoint ----
-        double sse = 0.0;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int64_t p = p0 + j * kWave;
-          const float out = nmodi ? s.O[0][j] : s.A[j];
-          gbar[j] = 0.0f;
-          if (p < a.D) {
-            const float e = out - a.Y[p];
-            sse += (double)(e * e);
-            gbar[j] = gt * 2.0f * e * a.inv_D;
-          }
-        }
-        sse = wave_sum_f64(sse);
+        // ---- forward: outputs, fitness, output adjoints ----
+        const double sse = wave_sum_f64(output_adjoints<K, VM, NO>(a, s, nmodi != 0, gt, p0, gbar));
         if (lane == 0) a.part[tile * a.P + t] = sse;
         if (nint == 0) {  // the tree is a single leaf
           const uint2 ins = a.prog[t * a.pstride];
           const int src = word_case(ins.x) - kLD;
           if (src >= kSrcX0)
-            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar[0]);
           else
-            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar[0]);
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[0][j];
         continue;
       }
 
       // ---- adjoint record q ----
-      const int modi = (w0 >> 6) & 1, c2first = (w0 >> 7) & 1;
+      const int modi = (w0 >> 6) & 1, c2first = (w0 >> 7) & 1, mo = (int)((w0 >> 22) & 3);
       const int pop = (w0 >> 8) & 1, push = (w0 >> 9) & 1;
       float adj[K];
       if (pop) {
@@ -315,7 +338,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
       for (int j = 0; j < K; ++j) {
         float da, db;
         partials(op, va[j], vb[j], da, db);
-        const float base = modi ? gbar[j] : adj[j];
+        const float base = modi ? out_adjoint<K, NO>(gbar, mo, j) : adj[j];
         a1[j] = base * da;
         a2[j] = base * db;
         if (modi) {  // the handed-up value is the rightmost child's
@@ -324,8 +347,8 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
         }
       }
       // leaves take their adjoint now; function children go on
-      if (k1 != kKindFunc) leaf_adjoint<K, VM>(a, st, t, p0, lane, k1, v1, w1, a1);
-      if (ar == 2 && k2 != kKindFunc) leaf_adjoint<K, VM>(a, st, t, p0, lane, k2, v2, w3, a2);
+      if (k1 != kKindFunc) leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, k1, v1, w1, a1);
+      if (ar == 2 && k2 != kKindFunc) leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, k2, v2, w3, a2);
       if (push) {  // both children are function nodes
         const float* second = c2first ? a1 : a2;
         const float* first = c2first ? a2 : a1;
@@ -374,21 +397,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
 // once per path head above it (the root's run included), instead of once
 // per function ancestor. The next record is loaded while the current one is
 // worked on.
-// Wave LDS: spill slots 4..7, then `cap` values (captures from the bottom,
-// pending adjoints from the top), then `cap` ints of pending code ranges.
+// Wave LDS: `cap` values (captures from the bottom, pending adjoints from the
+// top; during a run the tree's spill slots beyond the four in registers sit
+// just below the pending adjoints), then `cap` ints of pending code ranges.
 __device__ __forceinline__ uint4 load_path_record(rec_ptr p) { return make_uint4(p[0], p[1], p[2], p[3]); }
 
-template <int K, int VM>
-__global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
+template <int K, int VM, int NO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 4 ? 3 : 4))) void adjoint_path_kernel(
+    AdjArgs a) {
   extern __shared__ float s_lds[];
   constexpr int kTile = K * kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int W = blockDim.x / kWave;
   const int CAP = a.cap;
-  const int per_wave = (kMaxSlots - kRegSlots + CAP) * K * kWave;
-  float* spill = s_lds + wv * per_wave + lane;
-  float* vals = spill + (kMaxSlots - kRegSlots) * K * kWave;
+  const int per_wave = CAP * K * kWave;
+  float* vals = s_lds + wv * per_wave + lane;
   int* pinfo = (int*)(s_lds + W * per_wave) + wv * CAP;
 
   const int64_t b = blockIdx.x;
@@ -399,9 +423,9 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
   const int64_t t1 = min(a.P, t0 + a.tpu);
   const int64_t p0 = (int64_t)tile * kTile + lane;
 
-  AdjState<K, VM> st;
-  Regs<K, VM, 1>& s = st.s;
-  load_x_adj<K, VM>(a, s, p0);
+  AdjState<K, VM, NO> st;
+  Regs<K, VM, NO>& s = st.s;
+  load_x_adj<K, VM, NO>(a, s, p0);
 #pragma unroll
   for (int v = 0; v < VM; ++v)
 #pragma unroll
@@ -417,11 +441,13 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
     const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
     const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
     const int plen = __builtin_amdgcn_readfirstlane(inf[kInfoProgLen]);
+    // spill slots in LDS: those beyond the four in registers
+    const int xslots = max(__builtin_amdgcn_readfirstlane(inf[kInfoNeed]) - kRegSlots, 0);
     const float gt = a.grad_mse ? a.grad_mse[t] : 1.0f;
     prog_ptr prog = (prog_ptr)(a.prog + t * a.pstride);
     rec_ptr recs = (rec_ptr)(a.adj + t * (int64_t)a.Lmax * kAdjWords);
 
-    float gbar[K], cur[K], curv[K];
+    float gbar[NO][K], cur[K], curv[K];
     int csp = 0, psp = 0, q = 0;
     // the run ahead: the whole program but its END (the root's), or a light head's code range
     uint32_t rs = 0, rl = (uint32_t)(plen - 1);
@@ -433,40 +459,31 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           s.A[j] = 0.0f;
-          s.O[0][j] = 0.0f;
+#pragma unroll
+          for (int o = 0; o < NO; ++o) s.O[o][j] = 0.0f;
         }
         if (nint > 0) rn = load_path_record(recs);
       }
-      // the kernel's one interpreter call site
-      run_program<K, VM, 1, true, true>(prog + rs, s, spill, (int)rl, vals, &csp, rlev, CAP - psp);
+      // the kernel's one interpreter call site; the run's LDS spill slots sit just below the
+      // pending adjoints, above every capture the run can push
+      float* spill = vals + (CAP - psp - xslots) * (K * kWave);
+      run_program<K, VM, NO, true, true>(prog + rs, s, spill, (int)rl, vals, &csp, rlev, CAP - psp - xslots);
       if (root) {
         root = false;
-        // ---- forward: output, fitness partial, output adjoint ----
-        double sse = 0.0;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const int64_t p = p0 + j * kWave;
-          const float out = nmodi ? s.O[0][j] : s.A[j];
-          gbar[j] = 0.0f;
-          if (p < a.D) {
-            const float e = out - a.Y[p];
-            sse += (double)(e * e);
-            gbar[j] = gt * 2.0f * e * a.inv_D;
-          }
-        }
-        sse = wave_sum_f64(sse);
+        // ---- forward: outputs, fitness partial, output adjoints ----
+        const double sse = wave_sum_f64(output_adjoints<K, VM, NO>(a, s, nmodi != 0, gt, p0, gbar));
         if (lane == 0) a.part[tile * a.P + t] = sse;
         if (nint == 0) {  // the tree is a single leaf
           const uint2 ins = a.prog[t * a.pstride];
           const int src = word_case(ins.x) - kLD;
           if (src >= kSrcX0)
-            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, src - kSrcX0, 0u, gbar[0]);
           else
-            leaf_adjoint<K, VM>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, 0u, gbar[0]);
           break;
         }
 #pragma unroll
-        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[j];
+        for (int j = 0; j < K; ++j) cur[j] = nmodi ? 0.0f : gbar[0][j];
       }
       // the run's value is the current node's own value: the root's, or the light head's
 #pragma unroll
@@ -476,55 +493,82 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
       while (q < nint) {
         const uint32_t w0 = rn.x, w1 = rn.y, w2 = rn.z, w3 = rn.w;
         ++q;
-        const int op = w0 & 15, ar = (w0 >> 4) & 3, modi = (w0 >> 6) & 1;
-        const int ka = (w0 >> 7) & 3, kb = (w0 >> 9) & 3;
+        const int op = w0 & 15, ar = (w0 >> 4) & 3, modi = (w0 >> 6) & 1, mo = (int)((w3 >> 16) & 3);
+        const int pat = (w0 >> 7) & 15;
         const int va_var = (w0 >> 11) & 15, vb_var = (w0 >> 15) & 15;
-        const int eop = (w0 >> 19) & 1, has_light = (w0 >> 20) & 1, has_heavy = (w0 >> 21) & 1;
-        const uint32_t node_a = w0 >> 22, node_b = w3;
-        // children values: the light child's capture is on top, the heavy child's below it
-        float vl[K], vh[K], va[K], vb[K];
-        if (has_light) {
-          --csp;
-          const float* src = vals + csp * (K * kWave);
+        const int eop = (w0 >> 19) & 1;
+        const uint32_t node_a = w0 >> 22, node_b = w3 & 0xffffu;
+        const float ca = __uint_as_float(w1), cb = __uint_as_float(w2);
+        // children values by pattern: the light child's capture is on top, the heavy child's
+        // below it; a record with both pops two
+        float vh[K], va[K], vb[K];
 #pragma unroll
-          for (int j = 0; j < K; ++j) vl[j] = src[j * kWave];
-        }
-        if (has_heavy) {
-          --csp;
-          const float* src = vals + csp * (K * kWave);
+        for (int j = 0; j < K; ++j) vb[j] = 0.0f;
+        const float* top = vals + (csp - 1) * (K * kWave);
+        const float* below = vals + (csp - 2) * (K * kWave);
+        switch (pat) {
+          case kPatHL:
+          case kPatLH: {
+            float vl[K];
 #pragma unroll
-          for (int j = 0; j < K; ++j) vh[j] = src[j * kWave];
+            for (int j = 0; j < K; ++j) {
+              vl[j] = top[j * kWave];
+              vh[j] = below[j * kWave];
+            }
+            csp -= 2;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+              va[j] = pat == kPatHL ? vh[j] : vl[j];
+              vb[j] = pat == kPatHL ? vl[j] : vh[j];
+            }
+          } break;
+          case kPatHV:
+          case kPatHC:
+          case kPatH:
+#pragma unroll
+            for (int j = 0; j < K; ++j) va[j] = vh[j] = top[j * kWave];
+            csp -= 1;
+            if (pat == kPatHV) leaf_value<K, VM, NO>(s, kKindVar, vb_var, 0u, vb);
+            if (pat == kPatHC)
+#pragma unroll
+              for (int j = 0; j < K; ++j) vb[j] = cb;
+            break;
+          case kPatVH:
+          case kPatCH:
+#pragma unroll
+            for (int j = 0; j < K; ++j) vb[j] = vh[j] = top[j * kWave];
+            csp -= 1;
+            if (pat == kPatVH) leaf_value<K, VM, NO>(s, kKindVar, va_var, 0u, va);
+            else
+#pragma unroll
+              for (int j = 0; j < K; ++j) va[j] = ca;
+            break;
+          case kPatVV:
+          case kPatVC:
+          case kPatV:
+            leaf_value<K, VM, NO>(s, kKindVar, va_var, 0u, va);
+            if (pat == kPatVV) leaf_value<K, VM, NO>(s, kKindVar, vb_var, 0u, vb);
+            if (pat == kPatVC)
+#pragma unroll
+              for (int j = 0; j < K; ++j) vb[j] = cb;
+            break;
+          default:  // kPatCV, kPatCC, kPatC
+#pragma unroll
+            for (int j = 0; j < K; ++j) va[j] = ca;
+            if (pat == kPatCV) leaf_value<K, VM, NO>(s, kKindVar, vb_var, 0u, vb);
+            if (pat == kPatCC)
+#pragma unroll
+              for (int j = 0; j < K; ++j) vb[j] = cb;
+            break;
         }
         // the next record, loaded while this one is worked on
         if (q < nint) rn = load_path_record(recs + q * kPathWords);
-        if (ka == kPathHeavy) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) va[j] = vh[j];
-        } else if (ka == kPathLight) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) va[j] = vl[j];
-        } else {
-          leaf_value<K, VM>(s, ka, va_var, w1, va);
-        }
-#pragma unroll
-        for (int j = 0; j < K; ++j) vb[j] = 0.0f;
-        if (ar == 2) {
-          if (kb == kPathHeavy) {
-#pragma unroll
-            for (int j = 0; j < K; ++j) vb[j] = vh[j];
-          } else if (kb == kPathLight) {
-#pragma unroll
-            for (int j = 0; j < K; ++j) vb[j] = vl[j];
-          } else {
-            leaf_value<K, VM>(s, kb, vb_var, w2, vb);
-          }
-        }
         float a1[K], a2[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
           float da, db;
           partials_own(op, va[j], vb[j], curv[j], !modi, da, db);
-          const float base = modi ? gbar[j] : cur[j];
+          const float base = modi ? out_adjoint<K, NO>(gbar, mo, j) : cur[j];
           a1[j] = base * da;
           a2[j] = base * db;
           if (modi) {  // the handed-up value is the rightmost child's
@@ -532,28 +576,50 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
             else a1[j] += cur[j];
           }
         }
-        // leaves take their adjoints now
-        if (ka == kKindVar || ka == kKindConst) leaf_adjoint<K, VM>(a, st, t, p0, lane, ka, va_var, node_a, a1);
-        if (ar == 2 && (kb == kKindVar || kb == kKindConst))
-          leaf_adjoint<K, VM>(a, st, t, p0, lane, kb, vb_var, node_b, a2);
-        // the light child waits: its adjoint on the pending stack, its code range beside it
-        if (has_light) {
-          const float* al = (ka == kPathLight) ? a1 : a2;
+        // adjoints by pattern: leaves take theirs now, the light child's waits on the pending
+        // stack with its code range, the heavy child's becomes the current one
+        auto park = [&](const float* al, uint32_t info) {
           if (csp + psp + 1 <= CAP) {
             float* dadj = vals + (CAP - 1 - psp) * (K * kWave);
 #pragma unroll
             for (int j = 0; j < K; ++j) dadj[j * kWave] = al[j];
-            pinfo[psp] = (int)((ka == kPathLight) ? w1 : w2);
+            pinfo[psp] = (int)info;
           }
           ++psp;
-        }
-        if (has_heavy) {
-          const float* ah = (ka == kPathHeavy) ? a1 : a2;
+        };
+        auto follow = [&](const float* ah) {
 #pragma unroll
           for (int j = 0; j < K; ++j) {
             cur[j] = ah[j];
             curv[j] = vh[j];
           }
+        };
+        switch (pat) {
+          case kPatHL: park(a2, w2); follow(a1); break;
+          case kPatLH: park(a1, w1); follow(a2); break;
+          case kPatHV: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, vb_var, 0u, a2); follow(a1); break;
+          case kPatVH: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, va_var, 0u, a1); follow(a2); break;
+          case kPatHC: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_b, a2); follow(a1); break;
+          case kPatCH: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_a, a1); follow(a2); break;
+          case kPatVV:
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, va_var, 0u, a1);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, vb_var, 0u, a2);
+            break;
+          case kPatVC:
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, va_var, 0u, a1);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_b, a2);
+            break;
+          case kPatCV:
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_a, a1);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, vb_var, 0u, a2);
+            break;
+          case kPatCC:
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_a, a1);
+            leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_b, a2);
+            break;
+          case kPatH: follow(a1); break;
+          case kPatV: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindVar, va_var, 0u, a1); break;
+          default: leaf_adjoint<K, VM, NO>(a, st, t, p0, lane, kKindConst, 0, node_a, a1); break;  // kPatC
         }
         if (eop) {
           if (psp == 0) break;  // the tree's last path
@@ -590,18 +656,25 @@ __global__ __launch_bounds__(256) void adjoint_path_kernel(AdjArgs a) {
 
 // Both sweeps: heavy-path trees, then the trees whose sweep would not fit the
 // heavy-path kernel's LDS budget (each kernel skips the other's trees).
-template <int K, int VM>
-hipError_t launch_adjoint_kv(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s) {
+template <int K, int VM, int NO>
+hipError_t launch_adjoint_kvo(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s) {
   if (a.cap > 0) {
-    const size_t lds_p = (size_t)block_waves * ((kMaxSlots - kRegSlots + a.cap) * K * kWave * sizeof(float) +
-                                                a.cap * sizeof(int));
-    adjoint_path_kernel<K, VM><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds_p, s>>>(a);
+    const size_t lds_p = (size_t)block_waves * (a.cap * K * kWave * sizeof(float) + a.cap * sizeof(int));
+    adjoint_path_kernel<K, VM, NO><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds_p, s>>>(a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   const size_t lds = (size_t)block_waves * (kMaxSlots - kRegSlots + a.pend_slots) * K * kWave * sizeof(float);
-  adjoint_kernel<K, VM><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds, s>>>(a);
+  adjoint_kernel<K, VM, NO><<<dim3((unsigned)grid), dim3(block_waves * kWave), lds, s>>>(a);
   return hipGetLastError();
+}
+
+// Single-output populations carry one output accumulator and adjoint; multi-output ones
+// (2 to 4 outputs) carry four.
+template <int K, int VM>
+hipError_t launch_adjoint_kv(const AdjArgs& a, int block_waves, int64_t grid, hipStream_t s) {
+  return a.n_out == 1 ? launch_adjoint_kvo<K, VM, 1>(a, block_waves, grid, s)
+                      : launch_adjoint_kvo<K, VM, kMaxOutGrad>(a, block_waves, grid, s);
 }
 
 }  // namespace tgp

@@ -106,11 +106,13 @@ int pend_slots_for(int Lmax) {
   return std::max(1, lg);
 }
 
-// Values per wave the heavy-path adjoint sweep holds in LDS (captures and waiting light
-// children), by points per lane: 16 at 2 points (10 KB per wave with the spill slots; it
-// covers every tree of the depth-8 ramped populations), 12 at 4 (16 KB per wave: ten
-// waves per CU; 96% of depth-8 ramped trees). Trees whose sweep needs more go to the
-// recompute sweep.
+// Values per wave the heavy-path adjoint sweep holds in LDS (captures, waiting light
+// children and spill slots beyond the four in registers), by points per lane: 16 at 2
+// points (8 KB per wave; it covers every tree of the depth-8 ramped populations), 12 at
+// 4 (12 KB per wave, so LDS holds the twelve waves per CU the registers allow; 96% of
+// depth-8 ramped trees; 16 at 4 measured slower, its ten waves per CU costing more than
+// the recompute sweep of the other 4%). Trees whose sweep needs more go to the recompute
+// sweep.
 int adj_path_cap(int K) { return K == 2 ? 16 : 12; }
 
 int device_cus() {
@@ -142,8 +144,9 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
       c.flags |= flags;
     }
   }
-  // K = 16 exists for up to 2 variables, K = 8 for up to 8, K = 4 for all
-  const int kmax = d->V <= 2 ? 16 : (d->V <= 8 ? 8 : 4);
+  // K = 16 exists for up to 2 variables, K = 8 for up to 8, K = 4 for all (and for more than
+  // kMaxOutNarrow outputs)
+  const int kmax = n_out > kMaxOutNarrow ? 4 : (d->V <= 2 ? 16 : (d->V <= 8 ? 8 : 4));
   if (c.points_per_lane != 4 && c.points_per_lane != 8 && c.points_per_lane != 16) c.points_per_lane = std::min(8, kmax);
   c.points_per_lane = std::min(c.points_per_lane, kmax);
   const int64_t tile = 64LL * c.points_per_lane;
@@ -355,7 +358,8 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (st) return st;
   st = check_data(data, true);
   if (st) return st;
-  if (data->n_out != 1) return TGP_E_SHAPE;
+  const int n_out = data->n_out;
+  if (n_out > kMaxOutGrad) return TGP_E_UNSUPPORTED;
   const Layout L = layout(pop->P, pop->Lmax, part_tiles(data, true), grad_work_bytes(pop, data));
   st = check_ws(ws, ws_bytes, L.total);
   if (st) return st;
@@ -364,21 +368,22 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   if (cfg) c = *cfg;
   if (!cfg || c.mode == TGP_MODE_AUTO) {
     tgp_cfg cached{};
-    if (autotune_lookup(pop, data, 1, true, &cached)) {
+    if (autotune_lookup(pop, data, n_out, true, &cached)) {
       const int flags = c.flags;
       c = cached;
       c.flags |= flags;
     }
   }
   c.mode = TGP_MODE_POINT_MAJOR;
-  // 2 or 4 points per lane: at 2 the adjoint's registers and LDS halve and twice the waves fit
-  c.points_per_lane = c.points_per_lane == 2 ? 2 : 4;
+  // 2 or 4 points per lane: at 2 the adjoint's registers and LDS halve and twice the waves fit;
+  // multi-output populations (four output accumulators and adjoints) default to 2
+  if (c.points_per_lane != 2 && c.points_per_lane != 4) c.points_per_lane = n_out == 1 ? 4 : 2;
   // one wave per workgroup by default: the adjoint's LDS (spill slots and pending stack) bounds
   // residency, and small workgroups pack it best
   if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 1;
   char* w = (char*)ws;
   const int cap = (c.flags & TGP_FLAG_ADJ_RECOMPUTE) ? 0 : adj_path_cap(c.points_per_lane);
-  st = enqueue_plan(pop, data->V, 1, c, w, L, nullptr, nullptr, false, stream, true, 0, cap);
+  st = enqueue_plan(pop, data->V, n_out, c, w, L, nullptr, nullptr, false, stream, true, 0, cap);
   if (st) return st;
   if (launch_zero_f32(grad_value, pop->P, pop->row_stride, pop->row_stride, stream) != hipSuccess) return TGP_E_HIP;
   if (launch_zero_f32(grad_X, data->V, data->D, data->ldx, stream) != hipSuccess) return TGP_E_HIP;
@@ -397,6 +402,8 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
   aa.V = data->V;
   aa.D = data->D;
   aa.Y = data->Y;
+  aa.ldy = data->ldy;
+  aa.n_out = n_out;
   aa.inv_D = (float)(1.0 / (double)data->D);
   aa.info = (const int32_t*)(w + L.info);
   aa.prog = (const uint2*)(w + L.prog);
@@ -441,7 +448,6 @@ __attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* po
   if (st) return st;
   st = check_data(data, true);
   if (st) return st;
-  if (want_grad && n_out != 1) return TGP_E_SHAPE;
   const Layout L = layout(pop->P, pop->Lmax, part_tiles(data, want_grad != 0),
                           want_grad ? grad_work_bytes(pop, data) : 0);
   st = check_ws(ws, ws_bytes, L.total);
@@ -455,7 +461,7 @@ __attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) 
     case TGP_E_ARG: return "invalid argument (null pointer or bad scalar)";
     case TGP_E_SHAPE: return "inconsistent sizes or strides";
     case TGP_E_WORKSPACE: return "workspace missing, misaligned or too small";
-    case TGP_E_UNSUPPORTED: return "unsupported size (Lmax > 1024, V > 16 or n_out > 4)";
+    case TGP_E_UNSUPPORTED: return "unsupported size (Lmax > 1024, V > 16, n_out > 12, or n_out > 4 for gradients)";
     case TGP_E_HIP: return "HIP runtime error";
     case TGP_E_TOO_LARGE: return "the call needs more scratch than the static buffer of tgp_eval_mse_noalloc holds";
     default: return "unknown status";

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "tgp_autotune.h"
+#include "tgp_isa.h"
 
 namespace tgp {
 
@@ -77,6 +78,7 @@ tgp_status autotune_run(const tgp_pop* pop, const tgp_data* d, int n_out, bool g
     for (int k : {16, 8, 4}) {
       if (k == 16 && d->V > 2) continue;
       if (k == 8 && d->V > 8) continue;
+      if (k > 4 && n_out > kMaxOutNarrow) continue;  // many outputs: 4 points per lane only
       for (int bw : {1, 2, 4}) cands.push_back(tgp_cfg{TGP_MODE_TREE_MAJOR, bw, k, 1, 0});
       for (int tpu : {1, 4, 16, 64})
         cands.push_back(tgp_cfg{TGP_MODE_POINT_MAJOR, 4, k, tpu, 0});

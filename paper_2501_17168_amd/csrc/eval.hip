@@ -85,10 +85,10 @@ int occupancy_eval(int K, int VM, int NO, bool pred, int bw) {
 
 int eval_resident_waves(int K, int VM, int NO, bool pred, int bw) {
   // cached per instantiation and workgroup shape: index (K, VM, NO, pred, bw)
-  static std::atomic<int> cache[3][4][kMaxOut][2][3];
+  static std::atomic<int> cache[3][4][kMaxOutNarrow + 1][2][3];
   const int ki = K == 16 ? 2 : (K == 8 ? 1 : 0);
   const int vi = VM <= 2 ? 0 : (VM <= 4 ? 1 : (VM <= 8 ? 2 : 3));
-  const int oi = (NO < 1 ? 1 : (NO > kMaxOut ? kMaxOut : NO)) - 1;
+  const int oi = (NO < 1 ? 1 : (NO > kMaxOutNarrow ? kMaxOutNarrow + 1 : NO)) - 1;
   const int bi = bw >= 4 ? 2 : (bw >= 2 ? 1 : 0);
   std::atomic<int>& c = cache[ki][vi][oi][pred ? 1 : 0][bi];
   int w = c.load(std::memory_order_relaxed);

@@ -377,14 +377,19 @@ inline int occupancy_eval_kvo(bool pred, int bw) {
 }
 
 // The output accumulators are instantiated for exactly n_out outputs (1..4), so a
-// three-output population carries three accumulators, not four.
+// three-output population carries three accumulators, not four. Populations of 5 to
+// kMaxOut outputs (classification with many classes) run at 4 points per lane with
+// kMaxOut accumulators.
 template <int K, int VM>
 hipError_t launch_eval_kv(const EvalArgs& a, int NO, bool pred, int bw, int64_t grid, hipStream_t s) {
   switch (NO) {
     case 1: return launch_eval_kvo<K, VM, 1>(a, pred, bw, grid, s);
     case 2: return launch_eval_kvo<K, VM, 2>(a, pred, bw, grid, s);
     case 3: return launch_eval_kvo<K, VM, 3>(a, pred, bw, grid, s);
-    default: return launch_eval_kvo<K, VM, kMaxOut>(a, pred, bw, grid, s);
+    case 4: return launch_eval_kvo<K, VM, 4>(a, pred, bw, grid, s);
+    default:
+      if constexpr (K == 4) return launch_eval_kvo<K, VM, kMaxOut>(a, pred, bw, grid, s);
+      return hipErrorInvalidValue;
   }
 }
 
@@ -394,7 +399,10 @@ int occupancy_eval_kv(int NO, bool pred, int bw) {
     case 1: return occupancy_eval_kvo<K, VM, 1>(pred, bw);
     case 2: return occupancy_eval_kvo<K, VM, 2>(pred, bw);
     case 3: return occupancy_eval_kvo<K, VM, 3>(pred, bw);
-    default: return occupancy_eval_kvo<K, VM, kMaxOut>(pred, bw);
+    case 4: return occupancy_eval_kvo<K, VM, 4>(pred, bw);
+    default:
+      if constexpr (K == 4) return occupancy_eval_kvo<K, VM, kMaxOut>(pred, bw);
+      return 0;
   }
 }
 

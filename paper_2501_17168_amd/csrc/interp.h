@@ -76,13 +76,29 @@ __device__ __forceinline__ float src_val(const Regs<K, VM, NO>& s, int j, float 
 
 template <int K, int VM, int NO>
 __device__ __forceinline__ void add_out(Regs<K, VM, NO>& s, int o) {
-  // selects rather than branches, so every register index stays static
+  if constexpr (NO <= kMaxOutNarrow) {
+    // selects rather than branches, so every register index stays static
 #pragma unroll
-  for (int q = 0; q < NO; ++q) {
+    for (int q = 0; q < NO; ++q) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const float sum = s.O[q][j] + s.r[j];
-      s.O[q][j] = (q == o) ? sum : s.O[q][j];
+      for (int j = 0; j < K; ++j) {
+        const float sum = s.O[q][j] + s.r[j];
+        s.O[q][j] = (q == o) ? sum : s.O[q][j];
+      }
+    }
+  } else {
+    // many outputs: branch on the (wave-uniform) index, K adds instead of NO x K selects.
+    // The empty asm names the output, so the branches are not merged into one block with
+    // a computed register index (which would move the accumulators to scratch).
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+      if (q == o) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          s.O[q][j] += s.r[j];
+          asm volatile("; output %1 point %2" : "+v"(s.O[q][j]) : "n"(q), "n"(j));
+        }
+      }
     }
   }
 }
@@ -221,7 +237,7 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
       TGP_MB_CASE(4)
       TGP_MB_CASE(5)
       case kACC:
-        add_out<K, VM, NO>(s, aux);
+        add_out<K, VM, NO>(s, (int)(ins >> 32));
         break;
       case kNOP:
         break;

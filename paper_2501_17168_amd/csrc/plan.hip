@@ -246,12 +246,13 @@ __device__ void emit_path_records(const int* s_rec, const short* s_sz, const int
           node[k] = (uint32_t)c;
         }
       }
-      const uint32_t w0 = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) | (kinds[0] << 7) |
-                                     (kinds[1] << 9) | (vars[0] << 11) | (vars[1] << 15) |
+      const uint32_t w0 = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) |
+                                     (path_pattern(ar, kinds[0], kinds[1]) << 7) | (vars[0] << 11) | (vars[1] << 15) |
                                      ((hv < 0 ? 1 : 0) << 19) | ((lt >= 0 ? 1 : 0) << 20) |
                                      ((hv >= 0 ? 1 : 0) << 21)) |
                           (node[0] << 22);
-      *(uint4*)(recs + (int64_t)q * kPathWords) = make_uint4(w0, pay[0], pay[1], node[1]);
+      const uint32_t mo = (uint32_t)max(rec_modi(r), 0);
+      *(uint4*)(recs + (int64_t)q * kPathWords) = make_uint4(w0, pay[0], pay[1], node[1] | (mo << 16));
       ++q;
       h = hv;
     }
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           wd = load_word(src, unary_act(op, mo), s_pre[pos]);
         }
         put(prog, a.pstride, pos, mo >= 0 ? wd : cap(wd), pay);
-        if (mo >= 0) put(prog, a.pstride, pos + 1, cap(mkword(kACC, mo)), 0.0f);
+        if (mo >= 0) put(prog, a.pstride, pos + 1, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
         continue;
       }
       const int z1 = s_sz[c1];
@@ -620,7 +621,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       if (mo >= 0) {
         put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
         put(prog, a.pstride, pos + 1, mkword(kMB + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
-        put(prog, a.pstride, pos + 2, cap(mkword(kACC, mo)), 0.0f);
+        put(prog, a.pstride, pos + 2, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
       } else {
         put(prog, a.pstride, pos, cap(mkword(fused_case(op, a_first, src), aux)), pay);
       }
@@ -643,7 +644,9 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       int need = 0;
       if (lane == 0 && rec_kind(root) == kTypeFunc) need = path_need(s_rec, s_sz, s_stk);
       need = __shfl(need, 0, kWave);
-      if (need <= a.adj_cap) adj_fmt = kAdjFmtPath;
+      // spill slots beyond the registers' four sit between the captures and the pending
+      // adjoints during every run
+      if (need + max(need0 - kRegSlots, 0) <= a.adj_cap) adj_fmt = kAdjFmtPath;
     }
     if (adj_fmt == kAdjFmtPath) {
       // a single-leaf tree has no records
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         const int pop = (r & kRecPop) ? 1 : 0;
         wv[0] = (uint32_t)(rec_op(r) | (ar << 4) | ((rec_modi(r) >= 0 ? 1 : 0) << 6) | (c2first << 7) |
                            (pop << 8) | ((both_func ? 1 : 0) << 9) | (kinds[0] << 10) | (kinds[1] << 12) |
-                           (vars[0] << 14) | (vars[1] << 18));
+                           (vars[0] << 14) | (vars[1] << 18) | (max(rec_modi(r), 0) << 22));
         uint4* dst = (uint4*)(recs + (int64_t)q * kAdjWords);
         dst[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
         dst[1] = make_uint4(wv[4], 0u, 0u, 0u);

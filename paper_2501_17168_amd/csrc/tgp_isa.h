@@ -40,7 +40,9 @@ constexpr float kExpClamp = 20.0f; // exp argument clamp
 // ---- limits ----
 constexpr int kMaxLmax = 1024;
 constexpr int kMaxV = 16;
-constexpr int kMaxOut = 4;
+constexpr int kMaxOut = 12;        // outputs (Modi output index in 4 bits of the node record)
+constexpr int kMaxOutNarrow = 4;   // outputs with exact-count accumulator instantiations, any K
+constexpr int kMaxOutGrad = 4;     // outputs of gradient calls
 constexpr int kRegSlots = 4;       // spill slots held in registers
 constexpr int kMaxSlots = 8;       // spill slots in total (need <= 8 for len <= 1024)
 
@@ -60,7 +62,8 @@ constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 //   16..21  action after the case: kActUn | unary index applies a unary
 //           function to A (to the Modi register r instead with kActModi);
 //           kActStop ends the program
-//   22..24  aux: LDS slot of a kSrcRM source, output index of kACC
+//   22..24  aux: LDS slot of a kSrcRM source (kACC carries its output
+//           index in the payload instead)
 //   25      pre-load flag, 26..29 variable: after the spill and before the
 //           case, A = x[variable] (a binary node over two leaves is then
 //           one word)
@@ -82,7 +85,7 @@ constexpr int kDIVA = kSUBR + kNumSrc;    // A = A / src (protected)
 constexpr int kDIVR = kDIVA + kNumSrc;    // A = src / A (protected)
 constexpr int kMB = kDIVR + kNumSrc;      // Modi binary: r = op(A,T) (ord 0) or op(T,A) (ord 1),
                                           // A = the second operand's value: kMB + 2*bin_index + ord
-constexpr int kACC = kMB + 12;            // O[aux] += r
+constexpr int kACC = kMB + 12;            // O[o] += r, o in the payload word
 constexpr int kNOP = kACC + 1;            // nothing (the action bits do the work)
 constexpr int kEND = kNOP + 1;            // stop
 constexpr int kNumCases = kEND + 1;
@@ -126,7 +129,7 @@ constexpr uint32_t kHdrInvalid = 1u << 31, kHdrModi = 1u << 30, kHdrTree = (1u <
 // function nodes, whose value is recomputed by re-running their contiguous
 // code range [start, start + len) of the forward program.
 //   w0 = op | arity << 4 | modi << 6 | c2_first << 7 | pop << 8 | push << 9
-//        | kind1 << 10 | kind2 << 12 | var1 << 14 | var2 << 18
+//        | kind1 << 10 | kind2 << 12 | var1 << 14 | var2 << 18 | Modi output << 22
 //   w1, w2 = child 1: code start, code length (function) or node index,
 //            constant bits (constant)
 //   w3, w4 = child 2, likewise; w5..w7 = 0
@@ -152,16 +155,26 @@ constexpr int kKindFunc = 0, kKindVar = 1, kKindConst = 2, kKindNone = 3;
 // down; then, deepest light child first, each light child's own path and
 // what hangs below it (the light children wait on a pending stack).
 // A record is 4 words (kPathWords; the records of a tree are kPathWords apart):
-//   w0 = op | arity << 4 | modi << 6 | kind_a << 7 | kind_b << 9 | var_a << 11
+//   w0 = op | arity << 4 | modi << 6 | pattern << 7 | var_a << 11
 //        | var_b << 15 | end_of_path << 19 | has_light << 20 | has_heavy << 21
 //        | (node index of a constant child a) << 22
 //   w1 = child a's payload: a constant's bits, or for a light child
 //        code start | code length << 12 | light depth << 24
 //   w2 = child b's payload, likewise
-//   w3 = node index of a constant child b
-// kind: kPathHeavy, kKindVar, kKindConst or kPathLight (kind_b is unused for
-// a unary node).
+//   w3 = node index of a constant child b | Modi output << 16
+// pattern: the kinds of the children (heavy, light, variable, constant), one
+// of kPat*: for a binary node (child a, child b), for a unary node child a.
 constexpr int kPathHeavy = 0, kPathLight = 3, kPathWords = 4;
+enum : int { kPatHL = 0, kPatLH, kPatHV, kPatVH, kPatHC, kPatCH, kPatVV, kPatVC, kPatCV, kPatCC,
+             kPatH, kPatV, kPatC, kNumPat };
+__host__ __device__ constexpr int path_pattern(int arity, int kind_a, int kind_b) {
+  // kinds: kPathHeavy, kKindVar, kKindConst, kPathLight
+  return arity == 1 ? (kind_a == kPathHeavy ? kPatH : kind_a == kKindVar ? kPatV : kPatC)
+       : kind_a == kPathHeavy ? (kind_b == kPathLight ? kPatHL : kind_b == kKindVar ? kPatHV : kPatHC)
+       : kind_a == kPathLight ? kPatLH
+       : kind_a == kKindVar ? (kind_b == kPathHeavy ? kPatVH : kind_b == kKindVar ? kPatVV : kPatVC)
+       : (kind_b == kPathHeavy ? kPatCH : kind_b == kKindVar ? kPatCV : kPatCC);
+}
 // per-tree record format
 constexpr int kAdjFmtRecompute = 0, kAdjFmtPath = 1;
 

@@ -79,7 +79,9 @@ struct AdjArgs {
   int64_t ldx;
   int32_t V;
   int64_t D;
-  const float* Y;       // [D]
+  const float* Y;       // Y[o * ldy + p], o < n_out
+  int64_t ldy;
+  int32_t n_out;        // 1..4; Modi outputs of multi-output trees
   float inv_D;
   const int32_t* info;
   const uint2* prog;

@@ -67,6 +67,12 @@ WORKLOADS = {
              "linear projections",
         P=5_000, Lmax=256, V=13, D=178, funcs="F11", shape=("ramped", 2, 6), x=("normal", 0.0, 1.0),
         target="linear_argmax", sigma=0.0, n_out=3, seed=6, n_sample=None, modi_frac=1.0),
+    "yeast": dict(
+        desc="classification, Yeast-shaped: 5,000 multi-output trees (Modi outputs for 10 classes), ramped "
+             "half-and-half depth 2..6, 11 ops, 8 vars N(0,1), 1,484 points, labels = argmax of 10 random "
+             "linear projections",
+        P=5_000, Lmax=256, V=8, D=1_484, funcs="F11", shape=("ramped", 2, 6), x=("normal", 0.0, 1.0),
+        target="linear_argmax", sigma=0.0, n_out=10, seed=8, n_sample=None, modi_frac=1.0),
     "pagie": dict(
         desc="Pagie polynomial 1/(1+x^-4) + 1/(1+y^-4): trees ramped half-and-half depth 2..8, Lmax 512, "
              "{+,-,*,pdiv,sin,cos,tan}, 2 vars U(-5,5), no noise",

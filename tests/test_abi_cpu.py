@@ -46,7 +46,7 @@ def test_workspace_bytes():
     assert small > 0 and big > small
     assert ws_bytes(pop(10, 1025), data()) == 0          # Lmax beyond 1024
     assert ws_bytes(pop(10, 64), data(V=17)) == 0
-    assert ws_bytes(pop(10, 64), data(), n_out=5) == 0
+    assert ws_bytes(pop(10, 64), data(), n_out=13) == 0           # more than 12 outputs
     assert ws_bytes(pop(10, 64, stride=32), data()) == 0
     # program store: (3 Lmax + 2) instructions of 8 bytes per tree dominates
     assert ws_bytes(pop(1000, 1024), data()) >= 1000 * (3 * 1024 + 2) * 8
@@ -90,10 +90,10 @@ def test_multi_output_and_plan_host_checks():
     r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d), None, None, ctypes.c_void_p(FAKE), 10, None,
                                   ctypes.c_void_p(FAKE * 16), 1 << 40, None)
     assert r == _lib.TGP_E_SHAPE                            # ldp < D
-    d5 = data(n_out=5)
-    r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d5), None, ctypes.c_void_p(FAKE), None, 0, None,
+    d13 = data(n_out=13)
+    r = lib.tgp_eval_multi_output(ctypes.byref(p), ctypes.byref(d13), None, ctypes.c_void_p(FAKE), None, 0, None,
                                   ctypes.c_void_p(FAKE * 16), 1 << 40, None)
-    assert r == _lib.TGP_E_UNSUPPORTED
+    assert r == _lib.TGP_E_UNSUPPORTED                      # more than 12 outputs
     assert lib.tgp_plan(ctypes.byref(p), 0, 1, None, None, None, ctypes.c_void_p(FAKE * 16), 1 << 40,
                         None) == _lib.TGP_E_SHAPE
     assert lib.tgp_plan(ctypes.byref(p), 2, 1, None, None, None, None, 1 << 40, None) == _lib.TGP_E_WORKSPACE
@@ -181,8 +181,12 @@ def test_accuracy_and_gradient_tuning_host_checks():
     assert lib.tgp_eval_accuracy(ctypes.byref(p), ctypes.byref(d3), None, None, None, ws, 1 << 40,
                                  None) == _lib.TGP_E_ARG               # no output
     out = _lib.TgpCfg()
-    assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d3), 3, 1, ctypes.byref(out), ws, 1 << 40,
-                            None) == _lib.TGP_E_SHAPE                  # gradients need one output
+    d13 = data(n_out=13)
+    assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d13), 13, 1, ctypes.byref(out), ws, 1 << 40,
+                            None) == _lib.TGP_E_UNSUPPORTED            # more outputs than the library's 12
+    d5 = data(n_out=5)
+    assert lib.tgp_eval_mse_grad(ctypes.byref(p), ctypes.byref(d5), None, None, acc, None, None, None, ws,
+                                 1 << 40, None) == _lib.TGP_E_UNSUPPORTED   # gradients: at most 4 outputs
     assert lib.tgp_autotune(ctypes.byref(p), ctypes.byref(d1), 1, 1, ctypes.byref(out), ws, 64,
                             None) == _lib.TGP_E_WORKSPACE              # gradient workspace too small
 

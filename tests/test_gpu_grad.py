@@ -267,3 +267,42 @@ def test_deep_trees_mix_both_sweeps():
     rep_v = compare_grad_value(gv, ref, label="deep")
     rep_x = compare_grad_x(gx, ref, label="deep")
     print(f"deep trees: grad_value {rep_v}\n  grad_X {rep_x}", flush=True)
+
+
+def _multi_output_case(w, Y, k, label):
+    pop = dev_pop(w)
+    X = torch.from_numpy(w.X).to(DEV)
+    Yd = torch.from_numpy(Y).to(DEV)
+    mse, gv, gx = (t.cpu().numpy() for t in tgp.eval_mse_grad(pop, X, Yd, config=tgp.cfg(mode=2, points_per_lane=k)))
+    compare_fitness(mse, FitnessRef(w.type, w.value, w.size, w.X, Y, w.n_out), label=f"{label} fitness")
+    ref = GradRef(w.type, w.value, w.size, w.X, Y, w.n_out)
+    rep_v = compare_grad_value(gv, ref, label=label)
+    rep_x = compare_grad_x(gx, ref, label=label)
+    print(f"{label} K={k}: grad_value {rep_v}\n  grad_X {rep_x}", flush=True)
+    return gv, ref, rep_v
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_multi_output_gradients(k):
+    """Gradients of multi-output trees (§IV-C): the classification recipe's trees (every one with
+    Modi nodes for 3 outputs, depth <= 6, 13 variables) against 3 rows of regression targets.
+    Fitness sums the outputs' mean squared errors; a Modi node passes the adjoint of its own output
+    to its children. Fitness and gradients inside the oracle's envelopes."""
+    w = synth.workload("classify", P=400, D=600)
+    Y = np.random.default_rng(9).normal(size=(w.n_out, w.D)).astype(np.float32)
+    gv, ref, rep_v = _multi_output_case(w, Y, k, "multi-output")
+    assert np.any(gv[ref.const] != 0)
+    assert rep_v["tight"] >= 0.25 * rep_v["n"], rep_v
+
+
+def test_multi_output_gradients_long_trees():
+    """The batched recipe's population (lengths up to 1024, 10% Modi trees with 3 outputs, the rest
+    plain trees predicting (root, 0, 0)): most trees exceed the heavy-path budget, so both sweeps
+    run with four output adjoints. Every value inside its envelope; long trees leave few envelopes
+    within the 1e-3 bar (about 15% of the constant gradients here)."""
+    w, Y = work("batched", P=120, D=600)
+    assert w.n_out == 3 and len(w.meta["modi_trees"]) > 5
+    gv, ref, rep_v = _multi_output_case(w, Y, 2, "multi-output long")
+    modi = np.asarray(w.meta["modi_trees"])
+    assert np.any(gv[modi][ref.const[modi]] != 0)
+    assert rep_v["tight"] >= 0.1 * rep_v["n"], rep_v
