@@ -611,9 +611,11 @@ def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, lanes_
     """Gradient envelopes of sum_t g_t fitness_t over the listed rows.
 
     Returns (gv_lo, gv_hi, gv_nan [R][Lmax], gX_lo, gX_hi, gX_nan [V][D]). A constant's gradient
-    is a float32 sum of its per-point adjoints: lanes_k - 1 additions in a lane, 6 in a
-    wavefront, then one per point tile of 64 lanes_k points. A point's X gradient is a float32
-    sum over every variable leaf of the listed trees. Positions that are not constants are 0."""
+    is a float32 sum of its per-point adjoints: k - 1 additions in a lane of k points, 6 in a
+    wavefront, then one per point tile of 64 k points. lanes_k is one k or several; the bound
+    takes the longest of their addition chains, so it holds for each of them. A point's X
+    gradient is a float32 sum over every variable leaf of the listed trees. Positions that are
+    not constants are 0."""
     X = np.asarray(X, np.float64)
     V, D = X.shape
     Yd = np.asarray(Y, np.float64).reshape(n_out, D)
@@ -647,8 +649,8 @@ def grad(pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, lanes_
         for i in range(d.length):
             if d.kind[i] == 0:
                 nX[d.arg[i]] += 1
-    ntiles = -(-D // (64 * lanes_k))
-    h = lanes_k - 1 + 6 + ntiles
+    ks = (int(lanes_k),) if np.ndim(lanes_k) == 0 else tuple(int(k) for k in lanes_k)
+    h = max(k - 1 + 6 + -(-D // (64 * k)) for k in ks)
     with np.errstate(all="ignore"):
         gv_lo, gv_hi = _sum_iv(gv[0], gv[1], gv[2], h + D * 2.0 ** -29)
         hX = np.maximum(nX - 1, 0)[:, None] + nX[:, None] * 2.0 ** -29

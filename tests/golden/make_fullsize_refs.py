@@ -29,7 +29,7 @@ import synth  # noqa: E402
 OUT = os.path.join(HERE, "fullsize_refs.npz")
 WORKLOADS = ("plain", "hybrid", "dataparallel", "batched", "grad")
 GRAD_POINTS = 4096
-GRAD_LANES_K = 2
+GRAD_LANES_K = (2, 3, 4)
 
 
 def targets(w):

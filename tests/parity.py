@@ -70,10 +70,10 @@ def compare_fitness(got, ref, label=""):
 
 class GradRef:
     """float64 gradients and float32 envelopes of sum_t g_t fitness_t over a set of rows.
-    lanes_k: the fewest points per lane the device may use (more point tiles, so the widest
-    bound on the sums over points)."""
+    lanes_k: the points-per-lane values the device may use; the envelope bounds the sums over
+    points for each of them."""
 
-    def __init__(self, pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, lanes_k=2):
+    def __init__(self, pop_type, pop_value, pop_size, X, Y, n_out=1, rows=None, g=None, lanes_k=(2, 3, 4)):
         self.m64, self.gv64, self.gx64 = O.grad(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows, g=g)
         (self.gv_lo, self.gv_hi, self.gv_nan,
          self.gx_lo, self.gx_hi, self.gx_nan) = E.grad(pop_type, pop_value, pop_size, X, Y, n_out, rows=rows, g=g,

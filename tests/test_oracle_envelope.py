@@ -217,8 +217,8 @@ def test_tan_near_pole_is_unbounded():
                                      ("pagie", dict(P=120, D=2000)), ("batched", dict(P=60, D=700))])
 def test_gradient_envelope_holds_float32_evaluations(name, kw):
     w, Y = _work(name, **kw)
-    k = 2
-    glo, ghi, gnan, xlo, xhi, xnan = E.grad(w.type, w.value, w.size, w.X, Y, w.n_out, lanes_k=k)
+    ks = (2, 3, 4)
+    glo, ghi, gnan, xlo, xhi, xnan = E.grad(w.type, w.value, w.size, w.X, Y, w.n_out, lanes_k=ks)
     const = w.type == O.T_CONST
     for ulp, seed in ((0, 0), (3, 1), (3, 2)):
         _, gvs, gxs = O.grad(w.type, w.value, w.size, w.X, Y, w.n_out, shadow=True, ulp=ulp, seed=seed)
@@ -231,11 +231,27 @@ def test_gradient_envelope_holds_float32_evaluations(name, kw):
         d = O.decode(w.type[p], w.value[p], w.size[p], w.V, w.n_out)
         for j in np.nonzero(const[p])[0][:2]:
             lam = _const_adjoint_shadow(w, Y, p, j)
-            g32 = _wave_sum32(lam, k)
-            assert _inside(g32, glo[p, j], ghi[p, j], gnan[p, j]), (p, j, g32, glo[p, j], ghi[p, j])
+            for k in ks:
+                g32 = _wave_sum32(lam, k)
+                assert _inside(g32, glo[p, j], ghi[p, j], gnan[p, j]), (p, j, k, g32, glo[p, j], ghi[p, j])
             checked += 1
         del d
     assert checked > 10
+
+
+def test_gradient_envelope_over_several_lane_widths_is_the_widest():
+    """With several points-per-lane values the sum bound is the longest of their addition chains:
+    at 256 points four per lane make the longest chain (3 + 6 + 1 against 1 + 6 + 2 at two), at
+    4,096 two per lane do."""
+    for D, widest in ((256, 4), (4096, 2)):
+        w, Y = _work("grad", P=8, D=D)
+        one = {k: E.grad(w.type, w.value, w.size, w.X, Y, w.n_out, lanes_k=k) for k in (2, 3, 4)}
+        many = E.grad(w.type, w.value, w.size, w.X, Y, w.n_out, lanes_k=(2, 3, 4))
+        const = w.type == O.T_CONST
+        for k in (2, 3, 4):
+            assert (many[0][const] <= one[k][0][const]).all() and (many[1][const] >= one[k][1][const]).all()
+        assert np.array_equal(many[0][const], one[widest][0][const])
+        assert np.array_equal(many[1][const], one[widest][1][const])
 
 
 def _const_adjoint_shadow(w, Y, p, j):
