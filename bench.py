@@ -286,18 +286,10 @@ def compare_forms(tgp, torch, pop, X, Y, w, gpops_per_step, steps, tuned=None):
               "block_waves": tuned.get("block_waves", 4), "flags": 0}
     pers = tgp.cfg(pers_d)
     fwd(pers)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        fwd(pers)
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        fwd(pers)
-    ms_graph = timed_ms(torch, g.replay, steps)
+    g = tgp.GraphedCall(lambda: fwd(pers))
+    ms_graph = timed_ms(torch, g, steps)
     res["batched_persistent_graph"] = {"cfg": pers_d, "ms": ms_graph, "GPops/s": gpops_per_step / (ms_graph * 1e-3),
-                                       "vs_plain_fwd": ms_plain / ms_graph}
+                                       "vs_plain_fwd": ms_plain / ms_graph, "launch": g.mode}
     del g
 
     if w.n_out == 1:
@@ -530,16 +522,8 @@ def pagie_sweep(steps=5):
             ms["autotuned"] = timed_ms(torch, lambda: tgp.eval_mse(pop, X, Y, config=ct), steps)
             # the same call replayed from a hipGraph: device time without the host's per-call cost
             ws, out = tgp.Workspace(dev), torch.empty(P, device=dev)
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                tgp.eval_mse(pop, X, Y, config=ct, ws=ws, out=out)
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph):
-                tgp.eval_mse(pop, X, Y, config=ct, ws=ws, out=out)
-            ms["autotuned_graph"] = timed_ms(torch, graph.replay, steps)
+            graph = tgp.GraphedCall(lambda: tgp.eval_mse(pop, X, Y, config=ct, ws=ws, out=out))
+            ms["autotuned_graph"] = timed_ms(torch, graph, steps)
             del graph
             best = min(names.values(), key=ms.get)
             pop_best = min(ms["tree-major"], ms["persistent"])

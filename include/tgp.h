@@ -61,8 +61,9 @@ enum {
   TGP_E_WORKSPACE = -4,    /* workspace null, misaligned or smaller than needed   */
   TGP_E_UNSUPPORTED = -5,  /* sizes beyond the limits listed above                */
   TGP_E_HIP = -6,          /* a HIP runtime call or kernel launch failed          */
-  TGP_E_TOO_LARGE = -7     /* tgp_eval_mse_noalloc: the call needs more scratch than
+  TGP_E_TOO_LARGE = -7,    /* tgp_eval_mse_noalloc: the call needs more scratch than
                               the static buffer holds                             */
+  TGP_E_IO = -8            /* autotune cache file: cannot be opened or written     */
 };
 
 /* Per-tree status codes written to tree_status[t] (the smallest applicable):
@@ -96,7 +97,11 @@ typedef struct tgp_data {
 
 /* Launch configuration. Zero fields mean "default"; a NULL cfg means
  * "autotuned choice for this shape if tgp_autotune has cached one, else
- * the built-in default". */
+ * the built-in default". The environment variable TGP_FORCE_MODE
+ * ("tree-major" or 1, "point-major" or 2, "persistent" or 3) overrides the
+ * schedule of every forward evaluation call, whatever the cfg says (the
+ * trees per unit then take their default unless the schedule is unchanged);
+ * it is read at each call. */
 enum { TGP_MODE_AUTO = 0, TGP_MODE_TREE_MAJOR = 1, TGP_MODE_POINT_MAJOR = 2,
        TGP_MODE_PERSISTENT = 3 };
 /* Persistent mode: trees are ordered longest length bucket first; the waves
@@ -188,7 +193,7 @@ tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp
  * fitness and the values along the root's path of larger children, and every
  * smaller child's subtree is run once more for its own path. A tree whose
  * sweep would hold more values per lane at once than the sweep's LDS budget
- * (16 at 2 points per lane, 12 at 4; deep trees) is swept
+ * (16 at 2 or 3 points per lane, 12 at 4; deep trees) is swept
  * instead node by node, re-running each function child's subtree;
  * TGP_FLAG_ADJ_RECOMPUTE in cfg->flags sends every tree that way. Both give
  * the same gradient up to the order of float32 sums.
@@ -202,7 +207,7 @@ tgp_status tgp_eval_accuracy(const tgp_pop* pop, const tgp_data* data, const tgp
  * outputs' mean squared errors, a Modi node for output o passes
  * dL/dout_o * df/dchild to its children (§IV-C), and Y must hold n_out rows.
  * mse: device float32 [P]. cfg: mode is ignored (the sweep is point-major);
- * points_per_lane 2 or 4 (anything else: 4 for one output, 2 for several),
+ * points_per_lane 2, 3 or 4 (anything else: 3 for one output, 2 for several),
  * block_waves and trees_per_unit as for the forward calls. */
 tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp_cfg* cfg,
                              const float* grad_mse, float* mse, float* grad_value,
@@ -212,7 +217,7 @@ tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp
 /* Time the candidate launch configurations on this population and data,
  * keep the fastest in a process-wide cache keyed by the shape, and return
  * it in *out. Synchronises the stream; not capturable. With want_grad the
- * gradient call is tuned instead (its points per lane, 2 or 4, workgroup
+ * gradient call is tuned instead (its points per lane, 2 to 4, workgroup
  * shape and trees per unit;
  * the workspace sized with want_grad), and later
  * tgp_eval_mse_grad calls on this shape with a NULL or AUTO cfg use it.
@@ -220,6 +225,33 @@ tgp_status tgp_eval_mse_grad(const tgp_pop* pop, const tgp_data* data, const tgp
 tgp_status tgp_autotune(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
                         int32_t want_grad, tgp_cfg* out, void* ws, size_t ws_bytes,
                         hipStream_t stream);
+
+/* Persistent autotune cache (not in the paper). The cache key is the device's
+ * architecture name and compute-unit count, P, Lmax, V, D, n_out and the
+ * gradient flag. A cache file holds one JSON object per line:
+ *   {"arch":"gfx950","cus":256,"P":..,"Lmax":..,"V":..,"D":..,"n_out":..,
+ *    "grad":0|1,"mode":..,"block_waves":..,"points_per_lane":..,
+ *    "trees_per_unit":..,"flags":..}
+ * in exactly that key order. If the environment variable TGP_AUTOTUNE_CACHE
+ * names a file, the library reads it on its first cache lookup or tuning run
+ * and appends every new tgp_autotune result to it.
+ * tgp_autotune_cache_load: read a cache file into the process's cache (later
+ *   entries for a key replace earlier ones). A line that does not parse
+ *   exactly, or holds a value outside the limits (an unknown mode or flag, a
+ *   points-per-lane or workgroup size the call does not run, sizes beyond the
+ *   limits above), is skipped and counted in *n_rejected; such shapes keep
+ *   their default or tuned configuration. Both counts are optional.
+ *   TGP_E_IO if the file cannot be opened. Needs no device.
+ * tgp_autotune_cache_save: write every cached entry to path (through a
+ *   temporary file renamed over it). TGP_E_IO if it cannot be written. */
+tgp_status tgp_autotune_cache_load(const char* path, int32_t* n_loaded, int32_t* n_rejected);
+/* The configuration a call without one would take from the cache for this
+ * population, data, output count and gradient flag on the current device:
+ * *found = 1 and *out filled, or *found = 0. Reads the TGP_AUTOTUNE_CACHE file
+ * first if this process has not yet. Argument errors as tgp_autotune. */
+tgp_status tgp_autotune_cached(const tgp_pop* pop, const tgp_data* data, int32_t n_out,
+                               int32_t want_grad, tgp_cfg* out, int32_t* found);
+tgp_status tgp_autotune_cache_save(const char* path);
 
 /* ---- subtree exchange (§III-B) ----
  * exchange(T_old, k, T_new) replaces the subtree rooted at node k of T_old

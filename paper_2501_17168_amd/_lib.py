@@ -18,6 +18,7 @@ TGP_E_WORKSPACE = -4
 TGP_E_UNSUPPORTED = -5
 TGP_E_HIP = -6
 TGP_E_TOO_LARGE = -7
+TGP_E_IO = -8
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 MODE_AUTO, MODE_TREE_MAJOR, MODE_POINT_MAJOR, MODE_PERSISTENT = 0, 1, 2, 3
@@ -29,7 +30,8 @@ FLAG_ADJ_RECOMPUTE = 4
 EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_mse_noalloc", "tgp_eval_multi_output",
            "tgp_eval_accuracy",
            "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_generate", "tgp_status_str", "tgp_op_cost",
-           "tgp_profile", "tgp_profile_read")
+           "tgp_profile", "tgp_profile_read", "tgp_autotune_cache_load", "tgp_autotune_cache_save",
+           "tgp_autotune_cached")
 
 XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR = 0, 1, 2, 3
 XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM, XCHG_OUT_PADDED = 1, 2, 4
@@ -109,6 +111,12 @@ def load():
     lib.tgp_eval_mse_grad.restype = i32
     lib.tgp_autotune.argtypes = [P(TgpPop), P(TgpData), i32, i32, P(TgpCfg), vp, ctypes.c_size_t, vp]
     lib.tgp_autotune.restype = i32
+    lib.tgp_autotune_cache_load.argtypes = [ctypes.c_char_p, P(i32), P(i32)]
+    lib.tgp_autotune_cache_load.restype = i32
+    lib.tgp_autotune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.tgp_autotune_cache_save.restype = i32
+    lib.tgp_autotune_cached.argtypes = [P(TgpPop), P(TgpData), i32, i32, P(TgpCfg), P(i32)]
+    lib.tgp_autotune_cached.restype = i32
     lib.tgp_subtree_exchange.argtypes = [P(TgpPop), P(TgpPop), P(TgpExchange), vp, vp, vp, ctypes.c_int64, vp,
                                          vp]
     lib.tgp_subtree_exchange.restype = i32

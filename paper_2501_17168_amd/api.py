@@ -8,6 +8,7 @@ the NaN-padded prefix encoding of the paper's §III-A; X is [V][D] float32
 """
 
 import ctypes
+import os
 
 import torch
 
@@ -279,6 +280,33 @@ def autotune(pop, X, Y, n_out=None, want_grad=False, ws=None, stream=None):
     return out.as_dict()
 
 
+def autotune_cached(pop, X, Y, n_out=None, want_grad=False):
+    """The configuration a call without one would take from the autotune cache for this workload
+    on the current device (a cfg dict), or None."""
+    lib = _lib.load()
+    d, _ = _data(X, Y, n_out)
+    p = pop.abi()
+    out, found = TgpCfg(), ctypes.c_int32(0)
+    check(lib.tgp_autotune_cached(ctypes.byref(p), ctypes.byref(d), d.n_out, int(bool(want_grad)),
+                                  ctypes.byref(out), ctypes.byref(found)), "tgp_autotune_cached")
+    return out.as_dict() if found.value else None
+
+
+def autotune_cache_load(path):
+    """Read an autotune cache file (one JSON line per shape) into the process's cache.
+    Returns (entries loaded, lines rejected)."""
+    lib = _lib.load()
+    n_ok, n_bad = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib.tgp_autotune_cache_load(os.fsencode(path), ctypes.byref(n_ok), ctypes.byref(n_bad)),
+          "tgp_autotune_cache_load")
+    return n_ok.value, n_bad.value
+
+
+def autotune_cache_save(path):
+    """Write every cached launch configuration to an autotune cache file."""
+    check(_lib.load().tgp_autotune_cache_save(os.fsencode(path)), "tgp_autotune_cache_save")
+
+
 def _node_arg(t, name, B, uniform):
     if t is None:
         return None
@@ -398,3 +426,45 @@ class TreeMSE(torch.autograd.Function):
         _, gv, gx = eval_mse_grad(pop, X, y, grad_mse=grad_mse.contiguous().float(), want_grad_value=want_v,
                                   want_grad_x=want_x)
         return gv, None, None, gx, None
+
+
+class GraphedCall:
+    """A fixed sequence of library calls captured once in a HIP graph and replayed.
+
+    fn() enqueues the calls on the current stream, with every buffer passed in (ws= and out= for
+    the evaluation calls, so that a replay touches the same memory). It runs once on a side stream
+    first (capture needs warmed-up calls) and is then captured. If the capture fails (a call that
+    synchronises, allocates or is otherwise not capturable, or fn raising), the graph is dropped,
+    the reason kept in .reason, and every later call runs fn() eagerly instead: the results are
+    the same, only the launch overhead differs. .mode says which ("graph" or "eager")."""
+
+    def __init__(self, fn, warmup=1):
+        self.fn = fn
+        self.graph = None
+        self.reason = None
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        try:
+            with torch.cuda.graph(g):
+                fn()
+        except Exception as e:  # noqa: BLE001 - any capture failure falls back to eager calls
+            self.reason = f"{type(e).__name__}: {e}"
+            torch.cuda.synchronize()
+            return
+        self.graph = g
+
+    @property
+    def mode(self):
+        return "eager" if self.graph is None else "graph"
+
+    def __call__(self):
+        if self.graph is None:
+            self.fn()
+        else:
+            self.graph.replay()

@@ -18,6 +18,14 @@ hipError_t launch_adjoint(const AdjArgs& a, int K, int VM, int block_waves, int6
       default: return launch_adjoint_kv<2, 16>(a, block_waves, grid, s);
     }
   }
+  if (K == 3) {
+    switch (VM) {
+      case 2: return launch_adjoint_kv<3, 2>(a, block_waves, grid, s);
+      case 4: return launch_adjoint_kv<3, 4>(a, block_waves, grid, s);
+      case 8: return launch_adjoint_kv<3, 8>(a, block_waves, grid, s);
+      default: return launch_adjoint_kv<3, 16>(a, block_waves, grid, s);
+    }
+  }
   switch (VM) {
     case 2: return launch_adjoint_kv<4, 2>(a, block_waves, grid, s);
     case 4: return launch_adjoint_kv<4, 4>(a, block_waves, grid, s);

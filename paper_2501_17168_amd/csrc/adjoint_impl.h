@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
 __device__ __forceinline__ uint4 load_path_record(rec_ptr p) { return make_uint4(p[0], p[1], p[2], p[3]); }
 
 template <int K, int VM, int NO>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 4 ? 3 : 4))) void adjoint_path_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 3 ? 3 : 4))) void adjoint_path_kernel(
     AdjArgs a) {
   extern __shared__ float s_lds[];
   constexpr int kTile = K * kWave;

@@ -1,0 +1,6 @@
+// Instantiation of the adjoint kernel for K = 3 points per lane, up to 16 input variables.
+#include "adjoint_impl.h"
+
+namespace tgp {
+template hipError_t launch_adjoint_kv<3, 16>(const AdjArgs&, int, int64_t, hipStream_t);
+}  // namespace tgp

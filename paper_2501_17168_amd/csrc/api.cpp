@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -108,12 +109,12 @@ int pend_slots_for(int Lmax) {
 
 // Values per wave the heavy-path adjoint sweep holds in LDS (captures, waiting light
 // children and spill slots beyond the four in registers), by points per lane: 16 at 2
-// points (8 KB per wave; it covers every tree of the depth-8 ramped populations), 12 at
-// 4 (12 KB per wave, so LDS holds the twelve waves per CU the registers allow; 96% of
-// depth-8 ramped trees; 16 at 4 measured slower, its ten waves per CU costing more than
-// the recompute sweep of the other 4%). Trees whose sweep needs more go to the recompute
-// sweep.
-int adj_path_cap(int K) { return K == 2 ? 16 : 12; }
+// points (8 KB per wave; it covers every tree of the depth-8 ramped populations) and at 3
+// (12 KB per wave: the twelve waves per CU the registers allow fit), 12 at 4 (12 KB per
+// wave; 96% of depth-8 ramped trees; 16 at 4 measured slower, its ten waves per CU
+// costing more than the recompute sweep of the other 4%). Trees whose sweep needs more go
+// to the recompute sweep.
+int adj_path_cap(int K) { return K <= 3 ? 16 : 12; }
 
 int device_cus() {
   static int cus = -1;
@@ -131,8 +132,21 @@ int device_cus() {
 }
 
 
+// Schedule named by the environment variable TGP_FORCE_MODE ("tree-major" or 1,
+// "point-major" or 2, "persistent" or 3), or TGP_MODE_AUTO when it is unset or
+// names none of them.
+int forced_mode() {
+  const char* e = getenv("TGP_FORCE_MODE");
+  if (!e) return TGP_MODE_AUTO;
+  if (!strcmp(e, "1") || !strcmp(e, "tree-major")) return TGP_MODE_TREE_MAJOR;
+  if (!strcmp(e, "2") || !strcmp(e, "point-major")) return TGP_MODE_POINT_MAJOR;
+  if (!strcmp(e, "3") || !strcmp(e, "persistent")) return TGP_MODE_PERSISTENT;
+  return TGP_MODE_AUTO;
+}
+
 // Fill unset fields of a launch configuration (for a forward call with these
-// outputs and prediction flag).
+// outputs and prediction flag). TGP_FORCE_MODE overrides the schedule of the
+// given, cached or default configuration.
 tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_out, bool grad, bool pred) {
   tgp_cfg c{};
   if (in) c = *in;
@@ -143,6 +157,10 @@ tgp_cfg resolve(const tgp_cfg* in, const tgp_pop* pop, const tgp_data* d, int n_
       c = cached;
       c.flags |= flags;
     }
+  }
+  if (const int fm = forced_mode()) {
+    if (fm != c.mode) c.trees_per_unit = 0;  // trees per unit means something else per schedule
+    c.mode = fm;
   }
   // K = 16 exists for up to 2 variables, K = 8 for up to 8, K = 4 for all (and for more than
   // kMaxOutNarrow outputs)
@@ -375,9 +393,10 @@ __attribute__((visibility("default"))) tgp_status tgp_eval_mse_grad(
     }
   }
   c.mode = TGP_MODE_POINT_MAJOR;
-  // 2 or 4 points per lane: at 2 the adjoint's registers and LDS halve and twice the waves fit;
+  // 2 to 4 points per lane: fewer points per lane give more waves per CU, more give less scalar
+  // dispatch per point; 3 measured fastest for one output (three waves per SIMD), and
   // multi-output populations (four output accumulators and adjoints) default to 2
-  if (c.points_per_lane != 2 && c.points_per_lane != 4) c.points_per_lane = n_out == 1 ? 4 : 2;
+  if (c.points_per_lane < 2 || c.points_per_lane > 4) c.points_per_lane = n_out == 1 ? 3 : 2;
   // one wave per workgroup by default: the adjoint's LDS (spill slots and pending stack) bounds
   // residency, and small workgroups pack it best
   if (c.block_waves != 1 && c.block_waves != 2 && c.block_waves != 4) c.block_waves = 1;
@@ -455,6 +474,19 @@ __attribute__((visibility("default"))) tgp_status tgp_autotune(const tgp_pop* po
   return autotune_run(pop, data, n_out, want_grad != 0, out, ws, ws_bytes, stream);
 }
 
+__attribute__((visibility("default"))) tgp_status tgp_autotune_cached(const tgp_pop* pop, const tgp_data* data,
+                                                                      int32_t n_out, int32_t want_grad,
+                                                                      tgp_cfg* out, int32_t* found) {
+  if (!out || !found) return TGP_E_ARG;
+  tgp_status st = check_pop(pop);
+  if (st) return st;
+  st = check_data(data, true);
+  if (st) return st;
+  if (n_out < 1 || n_out > (want_grad ? kMaxOutGrad : kMaxOut)) return TGP_E_UNSUPPORTED;
+  *found = autotune_lookup(pop, data, n_out, want_grad != 0, out) ? 1 : 0;
+  return TGP_OK;
+}
+
 __attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) {
   switch (s) {
     case TGP_OK: return "ok";
@@ -464,6 +496,7 @@ __attribute__((visibility("default"))) const char* tgp_status_str(tgp_status s) 
     case TGP_E_UNSUPPORTED: return "unsupported size (Lmax > 1024, V > 16, n_out > 12, or n_out > 4 for gradients)";
     case TGP_E_HIP: return "HIP runtime error";
     case TGP_E_TOO_LARGE: return "the call needs more scratch than the static buffer of tgp_eval_mse_noalloc holds";
+    case TGP_E_IO: return "autotune cache file cannot be opened or written";
     default: return "unknown status";
   }
 }

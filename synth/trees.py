@@ -184,8 +184,8 @@ def exact_length(rng, lengths, funcs, V, Lmax, chunk=8192):
     funcs = np.asarray(funcs, np.int64)
     un = funcs[ARITY[funcs] == 1]
     bi = funcs[ARITY[funcs] == 2]
-    if un.size == 0:
-        raise ValueError("exact lengths need at least one unary op (even lengths are unreachable otherwise)")
+    if un.size == 0 and (lengths % 2 == 0).any():
+        raise ValueError("with binary ops only, a tree has an odd number of nodes")
     order = np.argsort(-lengths, kind="stable")
     Ls = lengths[order]
     T = np.empty((n, Lmax), np.float32)
@@ -206,12 +206,13 @@ def exact_length(rng, lengths, funcs, V, Lmax, chunk=8192):
             m = int(live_count[pos])
             r = L[:m] - pos
             s = open_[:m]
-            feas = np.stack([(s - 1 + a <= r - 1) & ((s - 1 + a >= 1) | (r == 1)) for a in (0, 1, 2)], 1)
+            feas = np.stack([(s - 1 + a <= r - 1) & ((s - 1 + a >= 1) | (r == 1)) & (a != 1 or un.size > 0)
+                             for a in (0, 1, 2)], 1)
             cnt = feas.sum(1)
             k = np.minimum((rng.random(m) * cnt).astype(np.int64), cnt - 1)
             cum = np.cumsum(feas, 1)
             a = np.argmax((cum > k[:, None]) & feas, axis=1)
-            uop = un[rng.integers(0, un.size, m)]
+            uop = un[rng.integers(0, un.size, m)] if un.size else np.zeros(m, np.int64)
             bop = bi[rng.integers(0, bi.size, m)]
             ttyp, tval, _ = _terminals(rng, m, V, np.zeros(m, np.int64), None)
             t_[pos, :m] = np.where(a == 0, ttyp, TYPE_FUNC)

@@ -57,7 +57,7 @@ WORKLOADS = {
         P=10_000, Lmax=256, V=2, D=2_000, funcs="F4", shape=("ramped", 2, 8), x=("uniform", -4.0, 4.0),
         target=("full", 4), sigma=0.01, n_out=1, seed=11, n_sample=None),
     "batched-arith": dict(
-        desc="200,000 trees, Lmax 1024, exact lengths log-uniform in [3,1024], {+,-,*,pdiv}, 4 vars "
+        desc="200,000 trees, Lmax 1024, exact lengths log-uniform in [3,1024] (even ones less one), {+,-,*,pdiv}, 4 vars "
              "U(-2,2), 4,096 points, 3 outputs (three hidden full(4) trees + N(0,0.01)), 10% Modi trees",
         P=200_000, Lmax=1024, V=4, D=4_096, funcs="F4", shape=("loguniform", 3, 1024), x=("uniform", -2.0, 2.0),
         target=("full", 4), sigma=0.01, n_out=3, seed=13, n_sample=2_000, modi_frac=0.1),
@@ -136,6 +136,8 @@ def _population(rng, r, P):
         lo, hi = r["shape"][1], r["shape"][2]
         L = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), P))).astype(np.int64)
         L = np.clip(L, lo, min(hi, r["Lmax"]))
+        if not (tr.ARITY[np.asarray(funcs)] == 1).any():
+            L = L - (L % 2 == 0)          # binary ops only: a tree has an odd number of nodes
         T, Vv, S = tr.exact_length(rng, L, funcs, r["V"], r["Lmax"])
         modi = None
         if r.get("modi_frac"):

@@ -192,7 +192,7 @@ def test_accuracy_and_gradient_tuning_host_checks():
 
 
 def test_status_strings():
-    for code in (0, -1, -2, -4, -5, -6, 7):
+    for code in (0, -1, -2, -4, -5, -6, -7, -8, 7):
         s = tgp.status_str(code)
         assert isinstance(s, str) and s
 
@@ -228,3 +228,52 @@ def test_eval_mse_noalloc_host_checks():
     assert call_noalloc(pop(fits + 1, 256), data(D=2000)) == _lib.TGP_E_TOO_LARGE
     assert call_noalloc(pop(200_000, 1024), data(V=4, D=4096)) == _lib.TGP_E_TOO_LARGE
     assert "static buffer" in _lib.status_str(_lib.TGP_E_TOO_LARGE)
+
+
+def _cache_line(**kw):
+    e = dict(arch="gfx950", cus=256, P=1000, Lmax=64, V=2, D=5000, n_out=1, grad=0, mode=1, block_waves=4,
+             points_per_lane=8, trees_per_unit=1, flags=0)
+    e.update(kw)
+    return ("{" + ",".join(f'"{k}":"{v}"' if k == "arch" else f'"{k}":{v}' for k, v in e.items()) + "}")
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The persistent autotune cache, on the host: exact lines load, every malformed or
+    out-of-range line is skipped and counted, and a save writes the loaded entries back in the
+    same line format (no device needed)."""
+    good = [_cache_line(), _cache_line(P=2000, mode=3, points_per_lane=4, trees_per_unit=2, flags=2),
+            _cache_line(grad=1, mode=2, points_per_lane=3, block_waves=1, trees_per_unit=64),
+            _cache_line(arch="gfx942", cus=304, D=70000, n_out=12, points_per_lane=4) + "  "]
+    bad = ["", "not json", _cache_line()[:-1],                       # truncated
+           _cache_line() + "x",                                      # trailing garbage
+           _cache_line(mode=0), _cache_line(mode=4),                 # unknown schedules
+           _cache_line(points_per_lane=3),                           # forward calls: 4, 8 or 16
+           _cache_line(grad=1, mode=2, points_per_lane=8),           # gradient calls: 2 to 4
+           _cache_line(grad=1, mode=1, points_per_lane=2),           # gradient calls are point-major
+           _cache_line(block_waves=3), _cache_line(trees_per_unit=0),
+           _cache_line(flags=8), _cache_line(grad=1, mode=2, points_per_lane=2, flags=2),
+           _cache_line(V=17), _cache_line(Lmax=2048), _cache_line(n_out=13),
+           _cache_line(grad=1, mode=2, points_per_lane=2, n_out=5),
+           _cache_line(P=0), _cache_line(D=-5), _cache_line(cus=0), _cache_line(grad=2),
+           _cache_line(arch="GFX950"), _cache_line(arch="gfx950:xnack-"),
+           _cache_line(arch="x" * 40),                               # longer than any architecture name
+           '{"cus":256,' + _cache_line()[1:],                        # keys out of order
+           "z" * 3000]                                               # longer than a line buffer
+    path = tmp_path / "cache.jsonl"
+    path.write_text("\n".join(good[:2] + bad + good[2:]) + "\n")
+    n_ok, n_bad = tgp.api.autotune_cache_load(str(path))
+    assert n_ok == len(good)
+    assert n_bad == len(bad) - 1          # the empty line is skipped without counting
+    out = tmp_path / "saved.jsonl"
+    tgp.api.autotune_cache_save(str(out))
+    saved = set(out.read_text().splitlines())
+    assert {g.strip() for g in good} <= saved
+    # what was saved loads again, line for line
+    n2, b2 = tgp.api.autotune_cache_load(str(out))
+    assert (n2, b2) == (len(saved), 0)
+    lib = tgp.load()
+    assert lib.tgp_autotune_cache_load(None, None, None) == _lib.TGP_E_ARG
+    assert lib.tgp_autotune_cache_save(None) == _lib.TGP_E_ARG
+    assert lib.tgp_autotune_cache_load(os.fsencode(tmp_path / "missing.jsonl"), None, None) == _lib.TGP_E_IO
+    assert lib.tgp_autotune_cache_save(os.fsencode(tmp_path / "no_dir" / "x.jsonl")) == _lib.TGP_E_IO
+    assert "cache" in _lib.status_str(_lib.TGP_E_IO)
