@@ -375,12 +375,12 @@ const char* tgp_status_str(tgp_status s);
  *   issue slot (from the same loop with 32 dependent FMAs added), is the
  *   cost. Synchronous; it allocates and frees a small
  *   device buffer. Returns TGP_E_ARG for a bad op or null output.
- * tgp_profile(enable): while enabled, every forward call records a HIP
- *   event pair around its evaluation-kernel launch on the caller's stream
- *   (creating the two events on the host).
+ * tgp_profile(enable): while enabled, every forward and gradient call
+ *   records a HIP event pair around its evaluation- or sweep-kernel launch
+ *   on the caller's stream (pairs are created once and reused after each
+ *   read; disabling releases the unused ones).
  * tgp_profile_read: waits for the recorded events, returns the summed
- *   evaluation-kernel time in ms and the number of launches, and clears
- *   the record. */
+ *   kernel time in ms and the number of launches, and clears the record. */
 tgp_status tgp_op_cost(int32_t op, double* slots);
 tgp_status tgp_profile(int32_t enable);
 tgp_status tgp_profile_read(double* total_ms, int64_t* launches);

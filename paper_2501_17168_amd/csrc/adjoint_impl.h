@@ -181,6 +181,20 @@ __device__ __forceinline__ float out_adjoint(const float (&gbar)[NO][K], int mo,
   return v;
 }
 
+// The trees among c0 .. c0 + 63 (below t1) that are valid and whose records are in format `fmt`,
+// as a wave-uniform bit mask: one load per lane and a ballot, so that a sweep skips the other
+// sweep's trees without a dependent scalar load per tree.
+__device__ __forceinline__ unsigned long long trees_of_format(const AdjArgs& a, int64_t c0, int64_t t1, int lane,
+                                                              int fmt) {
+  const int64_t t = c0 + lane;
+  bool want = false;
+  if (t < t1) {
+    const int32_t* inf = a.info + t * kInfoStride;
+    want = inf[kInfoStatus] == 0 && inf[kInfoAdjFmt] == fmt;
+  }
+  return __ballot(want);
+}
+
 }  // namespace
 
 template <int K, int VM, int NO>
@@ -211,11 +225,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a) {
     for (int j = 0; j < K; ++j) st.gx[v][j] = 0.0f;
 
   bool swept = false;  // this wave swept a tree (otherwise it has no grad_X to add)
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t c0 = t0; c0 < t1; c0 += kWave)
+  for (unsigned long long m = trees_of_format(a, c0, t1, lane, kAdjFmtRecompute); m; m &= m - 1) {
+    const int64_t t = c0 + __builtin_ctzll(m);
     const int32_t* inf = a.info + t * kInfoStride;
-    const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
-    if (status != 0) continue;
-    if (__builtin_amdgcn_readfirstlane(inf[kInfoAdjFmt]) != kAdjFmtRecompute) continue;
     swept = true;
     const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
     const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);
@@ -432,11 +445,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 3 ? 3 
     for (int j = 0; j < K; ++j) st.gx[v][j] = 0.0f;
 
   bool swept = false;  // this wave swept a tree (otherwise it has no grad_X to add)
-  for (int64_t t = t0; t < t1; ++t) {
+  for (int64_t c0 = t0; c0 < t1; c0 += kWave)
+  for (unsigned long long m = trees_of_format(a, c0, t1, lane, kAdjFmtPath); m; m &= m - 1) {
+    const int64_t t = c0 + __builtin_ctzll(m);
     const int32_t* inf = a.info + t * kInfoStride;
-    const int status = __builtin_amdgcn_readfirstlane(inf[kInfoStatus]);
-    if (status != 0) continue;
-    if (__builtin_amdgcn_readfirstlane(inf[kInfoAdjFmt]) != kAdjFmtPath) continue;
     swept = true;
     const int nmodi = __builtin_amdgcn_readfirstlane(inf[kInfoNModi]);
     const int nint = __builtin_amdgcn_readfirstlane(inf[kInfoNInternal]);

@@ -81,21 +81,30 @@ __global__ __launch_bounds__(256) void opcost_kernel(float* out, int iters, floa
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_ev;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_ev;    // recorded, not yet read
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_pool;  // read, kept for reuse
 
 }  // namespace
 
+// Event pairs are reused from one read to the next, so that a profiled call
+// costs two event records on the host, not two event creations.
 void profile_before(hipStream_t s, void** token) {
   *token = nullptr;
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (!g_prof_on) return;
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess) return;
-  if (hipEventCreate(&b) != hipSuccess) {
-    hipEventDestroy(a);
-    return;
+  if (!g_prof_pool.empty()) {
+    a = g_prof_pool.back().first;
+    b = g_prof_pool.back().second;
+    g_prof_pool.pop_back();
+  } else {
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return;
+    }
   }
-  hipEventRecord(a, s);
+  (void)hipEventRecord(a, s);
   g_prof_ev.emplace_back(a, b);
   *token = (void*)b;
 }
@@ -159,6 +168,13 @@ __attribute__((visibility("default"))) tgp_status tgp_op_cost(int32_t op, double
 __attribute__((visibility("default"))) tgp_status tgp_profile(int32_t enable) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof_on = enable != 0;
+  if (!g_prof_on) {  // release the reusable pairs (recorded ones wait for the next read)
+    for (auto& p : g_prof_pool) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    g_prof_pool.clear();
+  }
   return TGP_OK;
 }
 
@@ -176,8 +192,17 @@ __attribute__((visibility("default"))) tgp_status tgp_profile_read(double* total
     if (hipEventSynchronize(p.second) != hipSuccess || hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
       st = TGP_E_HIP;
     tot += ms;
-    hipEventDestroy(p.first);
-    hipEventDestroy(p.second);
+  }
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& p : ev) {
+      if (g_prof_on) {
+        g_prof_pool.push_back(p);
+      } else {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+      }
+    }
   }
   *total_ms = tot;
   *launches = (int64_t)ev.size();
