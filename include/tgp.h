@@ -381,7 +381,13 @@ const char* tgp_status_str(tgp_status s);
  *   read; disabling releases the unused ones).
  * tgp_profile_read: waits for the recorded events, returns the summed
  *   kernel time in ms and the number of launches, and clears the record. */
+/* tgp_op_apply: y[i] = unary operator `op` (sin, cos, tanh, exp, log or
+ *   tan: op ids 4-8 and 11, with the protection of exp and log) applied to
+ *   x[i] exactly as the evaluation kernels apply it; x and y are device
+ *   float32 [n]. Enqueued on `stream`; TGP_E_ARG for another op, a negative
+ *   n or a null array. For checking the operators' accuracy. */
 tgp_status tgp_op_cost(int32_t op, double* slots);
+tgp_status tgp_op_apply(int32_t op, const float* x, float* y, int64_t n, hipStream_t stream);
 tgp_status tgp_profile(int32_t enable);
 tgp_status tgp_profile_read(double* total_ms, int64_t* launches);
 

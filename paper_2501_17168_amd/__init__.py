@@ -14,6 +14,6 @@ from ._lib import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     Population, Workspace, cfg, workspace_bytes, plan, eval_mse, eval_mse_noalloc, eval_multi_output, eval_accuracy,
-    eval_mse_grad, autotune, autotune_cached, autotune_cache_load, autotune_cache_save, GraphedCall,
+    eval_mse_grad, autotune, autotune_cached, op_apply, autotune_cache_load, autotune_cache_save, GraphedCall,
     subtree_exchange, crossover, mutation, generate, TreeMSE,
 )

@@ -31,7 +31,7 @@ EXPORTS = ("tgp_workspace_bytes", "tgp_plan", "tgp_eval_mse", "tgp_eval_mse_noal
            "tgp_eval_accuracy",
            "tgp_eval_mse_grad", "tgp_autotune", "tgp_subtree_exchange", "tgp_generate", "tgp_status_str", "tgp_op_cost",
            "tgp_profile", "tgp_profile_read", "tgp_autotune_cache_load", "tgp_autotune_cache_save",
-           "tgp_autotune_cached")
+           "tgp_autotune_cached", "tgp_op_apply")
 
 XCHG_OK, XCHG_TOO_LONG, XCHG_BAD_OLD, XCHG_BAD_DONOR = 0, 1, 2, 3
 XCHG_OLD_UNIFORM, XCHG_NEW_UNIFORM, XCHG_OUT_PADDED = 1, 2, 4
@@ -122,6 +122,8 @@ def load():
     lib.tgp_subtree_exchange.restype = i32
     lib.tgp_generate.argtypes = [P(TgpGenCfg), ctypes.c_int64, i32, vp, vp, vp, ctypes.c_int64, vp, vp]
     lib.tgp_generate.restype = i32
+    lib.tgp_op_apply.argtypes = [i32, vp, vp, ctypes.c_int64, vp]
+    lib.tgp_op_apply.restype = i32
     lib.tgp_op_cost.argtypes = [i32, P(ctypes.c_double)]
     lib.tgp_op_cost.restype = i32
     lib.tgp_profile.argtypes = [i32]

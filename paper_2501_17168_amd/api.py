@@ -280,6 +280,18 @@ def autotune(pop, X, Y, n_out=None, want_grad=False, ws=None, stream=None):
     return out.as_dict()
 
 
+def op_apply(op, x, out=None, stream=None):
+    """The evaluation kernels' unary operator `op` (sin 4, cos 5, tanh 6, exp 7, log 8, tan 11, with
+    the protection of exp and log) applied elementwise to a contiguous float32 device tensor."""
+    _dev(x, "x")
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
+    y = torch.empty_like(x) if out is None else out
+    check(_lib.load().tgp_op_apply(int(op), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                   x.numel(), _stream(stream)), "tgp_op_apply")
+    return y
+
+
 def autotune_cached(pop, X, Y, n_out=None, want_grad=False):
     """The configuration a call without one would take from the autotune cache for this workload
     on the current device (a cfg dict), or None."""

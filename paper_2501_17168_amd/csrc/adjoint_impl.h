@@ -64,7 +64,7 @@ __device__ __forceinline__ void partials(int op, float a, float b, float& da, fl
       const float th = tanhf(a);
       da = 1.0f - th * th;
     } break;
-    case kOpExp: da = (a >= -kExpClamp && a <= kExpClamp) ? expf(a) : 0.0f; break;
+    case kOpExp: da = (a >= -kExpClamp && a <= kExpClamp) ? exp_clamped(a) : 0.0f; break;
     case kOpLog: da = a == 0.0f ? 0.0f : copysignf(1.0f, a) / (fabsf(a) + kLogEps); break;
     default: {  // tan
       const float tn = tanf(a);

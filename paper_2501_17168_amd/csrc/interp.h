@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "ops.h"
 #include "tgp_kernels.h"
 
 namespace tgp {
@@ -58,10 +59,8 @@ __device__ __forceinline__ float un_op(float a) {
   if constexpr (U == 0) return sinf(a);
   else if constexpr (U == 1) return cosf(a);
   else if constexpr (U == 2) return tanhf(a);
-  else if constexpr (U == 3) {
-    const float c = a > kExpClamp ? kExpClamp : (a < -kExpClamp ? -kExpClamp : a);
-    return expf(c);
-  } else if constexpr (U == 4) return logf(fabsf(a) + kLogEps);
+  else if constexpr (U == 3) return exp_clamped(a);
+  else if constexpr (U == 4) return log_positive(fabsf(a) + kLogEps);
   else return tanf(a);
 }
 

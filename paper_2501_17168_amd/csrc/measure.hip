@@ -10,10 +10,13 @@
 //    around each evaluation-kernel launch on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
 #include "tgp.h"
+#include "interp.h"
+#include "ops.h"
 #include "tgp_isa.h"
 #include "tgp_kernels.h"
 
@@ -46,10 +49,8 @@ __device__ __forceinline__ float apply(float x, float c) {
   else if constexpr (OP == kOpSin) return sinf(x);
   else if constexpr (OP == kOpCos) return cosf(x);
   else if constexpr (OP == kOpTanh) return tanhf(x);
-  else if constexpr (OP == kOpExp) {
-    const float e = x > kExpClamp ? kExpClamp : (x < -kExpClamp ? -kExpClamp : x);
-    return expf(e);
-  } else if constexpr (OP == kOpLog) return logf(fabsf(x) + kLogEps);
+  else if constexpr (OP == kOpExp) return exp_clamped(x);
+  else if constexpr (OP == kOpLog) return log_positive(fabsf(x) + kLogEps);
   else if constexpr (OP == kOpMax) return fmaxf(x, c);
   else if constexpr (OP == kOpMin) return fminf(x, c);
   else return tanf(x);
@@ -77,6 +78,15 @@ __global__ __launch_bounds__(256) void opcost_kernel(float* out, int iters, floa
 #pragma unroll
   for (int k = 0; k < 8; ++k) s += acc[k];
   out[t] = s;
+}
+
+// y[i] = the interpreter's unary operator U applied to x[i] (as the
+// evaluation kernels apply it).
+template <int U>
+__global__ __launch_bounds__(256) void op_apply_kernel(const float* __restrict__ x, float* __restrict__ y,
+                                                       int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = interp::un_op<U>(x[i]);
 }
 
 std::mutex g_prof_mu;
@@ -163,6 +173,33 @@ __attribute__((visibility("default"))) tgp_status tgp_op_cost(int32_t op, double
   if (err != hipSuccess) return TGP_E_HIP;
   *slots = (t_op - t_null) / ((t_unit - t_null) / kUnitOps);
   return TGP_OK;
+}
+
+__attribute__((visibility("default"))) tgp_status tgp_op_apply(int32_t op, const float* x, float* y, int64_t n,
+                                                               hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!x || !y))) return TGP_E_ARG;
+  int u = -1;
+  switch (op) {
+    case kOpSin: u = 0; break;
+    case kOpCos: u = 1; break;
+    case kOpTanh: u = 2; break;
+    case kOpExp: u = 3; break;
+    case kOpLog: u = 4; break;
+    case kOpTan: u = 5; break;
+    default: return TGP_E_ARG;
+  }
+  if (n == 0) return TGP_OK;
+  const int threads = 256;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + threads - 1) / threads, 16384);
+  switch (u) {
+    case 0: op_apply_kernel<0><<<blocks, threads, 0, stream>>>(x, y, n); break;
+    case 1: op_apply_kernel<1><<<blocks, threads, 0, stream>>>(x, y, n); break;
+    case 2: op_apply_kernel<2><<<blocks, threads, 0, stream>>>(x, y, n); break;
+    case 3: op_apply_kernel<3><<<blocks, threads, 0, stream>>>(x, y, n); break;
+    case 4: op_apply_kernel<4><<<blocks, threads, 0, stream>>>(x, y, n); break;
+    default: op_apply_kernel<5><<<blocks, threads, 0, stream>>>(x, y, n); break;
+  }
+  return hipGetLastError() == hipSuccess ? TGP_OK : TGP_E_HIP;
 }
 
 __attribute__((visibility("default"))) tgp_status tgp_profile(int32_t enable) {

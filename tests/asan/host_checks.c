@@ -120,6 +120,16 @@ static void exchange_and_generation_calls(void) {
   EXPECT(tgp_generate(&g, 0, 64, NULL, NULL, NULL, 64, NULL, NULL), TGP_OK);
 }
 
+static void measurement_calls(void) {
+  float* x = (float*)FAKE(9);
+  EXPECT(tgp_op_apply(0, x, x, 10, NULL), TGP_E_ARG);
+  EXPECT(tgp_op_apply(12, x, x, 10, NULL), TGP_E_ARG);
+  EXPECT(tgp_op_apply(7, x, x, -1, NULL), TGP_E_ARG);
+  EXPECT(tgp_op_apply(7, NULL, x, 10, NULL), TGP_E_ARG);
+  EXPECT(tgp_op_apply(7, NULL, NULL, 0, NULL), TGP_OK);
+  EXPECT(tgp_op_cost(12, NULL), TGP_E_ARG);
+}
+
 static void status_strings(void) {
   for (int s = -9; s <= 2; ++s) {
     const char* t = tgp_status_str((tgp_status)s);
@@ -187,6 +197,7 @@ int main(int argc, char** argv) {
   }
   evaluation_calls();
   exchange_and_generation_calls();
+  measurement_calls();
   status_strings();
   cache_files(argv[1]);
   if (!g_fail) printf("host checks passed\n");

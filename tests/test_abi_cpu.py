@@ -277,3 +277,16 @@ def test_autotune_cache_file_round_trip(tmp_path):
     assert lib.tgp_autotune_cache_load(os.fsencode(tmp_path / "missing.jsonl"), None, None) == _lib.TGP_E_IO
     assert lib.tgp_autotune_cache_save(os.fsencode(tmp_path / "no_dir" / "x.jsonl")) == _lib.TGP_E_IO
     assert "cache" in _lib.status_str(_lib.TGP_E_IO)
+
+
+def test_op_apply_host_checks():
+    """tgp_op_apply rejects binary and unknown ops, negative sizes and null arrays before any
+    device work; an empty call does nothing."""
+    lib = tgp.load()
+    f = ctypes.c_void_p(FAKE)
+    for op in (0, 3, 9, 10, 12, -1):
+        assert lib.tgp_op_apply(op, f, f, 10, None) == _lib.TGP_E_ARG
+    assert lib.tgp_op_apply(7, f, f, -1, None) == _lib.TGP_E_ARG
+    assert lib.tgp_op_apply(7, None, f, 10, None) == _lib.TGP_E_ARG
+    assert lib.tgp_op_apply(7, f, None, 10, None) == _lib.TGP_E_ARG
+    assert lib.tgp_op_apply(7, None, None, 0, None) == _lib.TGP_OK
