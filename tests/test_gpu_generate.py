@@ -34,6 +34,11 @@ CASES = [
     (500, 16, 2, [0, 2], "full", 0, 6, 3, (-5.0, 5.0), None, None, 8, 0),
     (777, 128, 5, [3, 4, 8, 9], "ramped", 1, 7, 5, (0.0, 10.0), 0.6, 0.3, 2, 123_456),
     (130, 1024, 1, [0, 1, 2, 3], "grow", 0, 12, 0, (-5.0, 5.0), 0.7, None, 8, 0),
+    # ramped trees run in waves of one (depth limit, method) class: classes barely filled, a
+    # single depth limit, and a first tree that does not start a class cycle
+    (5, 64, 2, F7, "ramped", 3, 3, 9, (-5.0, 5.0), None, None, 8, 7),
+    (65, 32, 2, F11, "ramped", 0, 8, 11, (-5.0, 5.0), None, None, 8, 1_000_001),
+    (1, 16, 1, F7, "ramped", 1, 4, 12, (-5.0, 5.0), None, None, 8, 3),
 ]
 
 
