@@ -63,6 +63,17 @@ __device__ __forceinline__ int own_code(int r) {
   return 1;                                     // fused binary op | (LD or NOP) + action
 }
 
+// Forward programs: a unary node whose child is a binary function node puts
+// its function in the action bits of that child's last word (the fused op
+// word, or the ACC of a Modi child), which never carries an action of its
+// own, instead of a NOP word; it then emits nothing, or only its ACC when it
+// is a Modi node. Gradient programs keep the NOP: there the child's last word
+// captures the child's value for the adjoint sweep.
+__device__ __forceinline__ bool folds_into_child(int r, int rc1, bool adj) {
+  return !adj && rec_kind(r) == kTypeFunc && rec_arity(r) == 1 && rec_kind(rc1) == kTypeFunc &&
+         rec_arity(rc1) == 2;
+}
+
 // action bits of a unary node: its function, for the Modi register if Modi
 __device__ __forceinline__ int unary_act(int op, int mo) {
   return kActUn | un_index(op) | (mo >= 0 ? kActModi : 0);
@@ -441,7 +452,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           if (rec_kind(r) == kTypeFunc) {
             const int c1 = i + 1;
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
-            int cc = own_code(r);
+            int cc = own_code(r) - (folds_into_child(r, s_rec[c1], a.adj) ? 1 : 0);
             if (rec_arity(r) == 2) {
               const int r2 = s_rec[c1 + s_sz[c1]];
               const bool l2 = rec_kind(r2) != kTypeFunc;
@@ -543,11 +554,17 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     __syncthreads();
 
     // ---- pass 6: emission ----
+    // the program's last word (the root's, or a folded unary root's child's) also stops the run,
+    // so no END word is dispatched
+    const int last = prog_len - 2;
+    auto emit = [&](int q, uint32_t w, float pay) {
+      put(prog, a.pstride, q, q == last ? w | ((uint32_t)kActStop << kActShift) : w, pay);
+    };
     if (rec_kind(root) != kTypeFunc) {
       if (lane == 0) {
         int src; float pay;
         leaf_src(root, vrow[0], src, pay);
-        put(prog, a.pstride, 0, mkword(kLD + src), pay);  // a leaf root has no spill
+        emit(0, mkword(kLD + src), pay);  // a leaf root has no spill
       }
     }
     for (int ch = 0; ch < nch; ++ch) {
@@ -562,13 +579,18 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int capl = (a.adj && i > 0) ? bs - ((r & kRecLight) ? 1 : 0) : -1;
       auto cap = [capl](uint32_t w) { return capl >= 0 ? with_capture(w, capl) : w; };
       const int cs = (s_E[i + s_sz[i]] - s_E[i]) & 0xffff;
-      const int oc = own_code(r);
-      const int pos = st + cs - oc;  // first own instruction
       const int op = rec_op(r);
       const int mo = rec_modi(r);
       const int c1 = i + 1;
       const int r1 = s_rec[c1];
       const bool l1 = rec_kind(r1) != kTypeFunc;
+      const bool folded = folds_into_child(r, r1, a.adj);
+      const int oc = own_code(r) - (folded ? 1 : 0);
+      const int pos = st + cs - oc;  // first own instruction
+      if (folded) {
+        if (mo >= 0) emit(pos, mkword(kACC), __uint_as_float((uint32_t)mo));
+        continue;
+      }
       if (rec_arity(r) == 1) {
         // over a leaf: its load carries the function; otherwise a NOP does
         uint32_t wd = mkword(kNOP, 0, unary_act(op, mo));
@@ -578,14 +600,19 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           leaf_src(r1, vrow[c1], src, pay);
           wd = load_word(src, unary_act(op, mo), s_pre[pos]);
         }
-        put(prog, a.pstride, pos, mo >= 0 ? wd : cap(wd), pay);
-        if (mo >= 0) put(prog, a.pstride, pos + 1, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
+        emit(pos, mo >= 0 ? wd : cap(wd), pay);
+        if (mo >= 0) emit(pos + 1, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
         continue;
       }
       const int z1 = s_sz[c1];
       const int c2 = c1 + z1;
       const int r2 = s_rec[c2];
       const bool l2 = rec_kind(r2) != kTypeFunc;
+      // the function of a unary parent folded into this node's last word (node i - 1 is the
+      // parent exactly when it is a unary function node)
+      const int rp = i > 0 ? s_rec[i - 1] : 0;
+      const uint32_t pact =
+          (i > 0 && folds_into_child(rp, r, a.adj)) ? (uint32_t)unary_act(rec_op(rp), rec_modi(rp)) << kActShift : 0u;
       int src, aux = 0;
       float pay = 0.0f;
       bool a_first;  // A holds the first operand and src the second
@@ -595,14 +622,14 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         const int pv = v1 ? rec_var(r1) : rec_var(r2);
         leaf_src(v1 ? r2 : r1, vrow[v1 ? c2 : c1], src, pay);
         a_first = v1;
-        uint32_t wd = with_preload(mkword(fused_case(op, a_first, src), aux), pv);
+        uint32_t wd = with_preload(mkword(fused_case(op, a_first, src), aux), pv) | pact;
         if (s_pre[pos]) wd = with_spill(wd, s_pre[pos] - 1);
-        put(prog, a.pstride, pos, cap(wd), pay);
+        emit(pos, cap(wd), pay);
         continue;
       } else if (l1 && l2) {
         int s1; float p1;
         leaf_src(r1, vrow[c1], s1, p1);
-        put(prog, a.pstride, st, load_word(s1, 0, s_pre[st]), p1);
+        emit(st, load_word(s1, 0, s_pre[st]), p1);
         leaf_src(r2, vrow[c2], src, pay);
         a_first = true;
       } else if (l1) {
@@ -619,16 +646,18 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
         a_first = !f1;  // the first-evaluated child is in the slot
       }
       if (mo >= 0) {
-        put(prog, a.pstride, pos, mkword(kTLD + src, aux), pay);
-        put(prog, a.pstride, pos + 1, mkword(kMB + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
-        put(prog, a.pstride, pos + 2, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
+        emit(pos, mkword(kTLD + src, aux), pay);
+        emit(pos + 1, mkword(kMB + 2 * bin_index(op) + (a_first ? 0 : 1)), 0.0f);
+        emit(pos + 2, cap(mkword(kACC) | pact), __uint_as_float((uint32_t)mo));
       } else {
-        put(prog, a.pstride, pos, cap(mkword(fused_case(op, a_first, src), aux)), pay);
+        emit(pos, cap(mkword(fused_case(op, a_first, src), aux) | pact), pay);
       }
     }
     if (lane == 0) {
+      // END words: a guard after the last word, and the word the interpreter's one-word lookahead
+      // reads
       put(prog, a.pstride, prog_len - 1, mkword(kEND), 0.0f);
-      put(prog, a.pstride, prog_len, mkword(kEND), 0.0f);  // read by the interpreter's one-word lookahead
+      put(prog, a.pstride, prog_len, mkword(kEND), 0.0f);
     }
 
     // ---- pass 7: adjoint records (gradient calls only) ----
