@@ -138,7 +138,7 @@ __device__ __forceinline__ void eval_tree(const EvalArgs& a, Regs<K, VM, NO>& s,
       for (int j = 0; j < K; ++j) s.O[q][j] = 0.0f;
   }
   // every program starts by loading A
-  run_from<K, VM, NO>((prog_ptr)(a.prog + t * a.pstride), first, s, spill);
+  run_from<K, VM, NO, false, false, true>((prog_ptr)(a.prog + t * a.pstride), first, s, spill);
   between();
 
   if constexpr (PRED) {

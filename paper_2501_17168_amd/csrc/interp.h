@@ -107,13 +107,63 @@ __device__ __forceinline__ void add_out(Regs<K, VM, NO>& s, int o) {
 // with scalar loads
 typedef const __attribute__((address_space(4))) unsigned long long* prog_ptr;
 
+// One action: v = f(A) for the unary function in bits 0..2 of `un`; a Modi
+// node's value goes to r while A keeps the child value it hands up, any
+// other node's replaces A. Unary (transcendental) functions run here, after
+// the dispatch switch: the library implementations branch per lane, and
+// keeping those divergent branches out of the switch keeps the switch a
+// purely scalar branch tree (no per-lane flow merges that copy the register
+// state).
+template <int K, int VM, int NO>
+__device__ __forceinline__ void apply_unary(Regs<K, VM, NO>& s, int un) {
+  float v[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) v[j] = s.A[j];
+  switch (un & 7) {
+    case 0:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<0>(v[j]);
+      break;
+    case 1:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<1>(v[j]);
+      break;
+    case 2:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<2>(v[j]);
+      break;
+    case 3:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<3>(v[j]);
+      break;
+    case 4:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<4>(v[j]);
+      break;
+    default:
+#pragma unroll
+      for (int j = 0; j < K; ++j) v[j] = un_op<5>(v[j]);
+      break;
+  }
+  if (un & kActModi) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) s.r[j] = v[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) s.A[j] = v[j];
+  }
+}
+
 // Interpret one program on this lane's K points. `spill` points at this
 // wave's LDS spill area [kMaxSlots - kRegSlots][K][64], offset by the lane.
 // The next instruction word is fetched while the current one executes; the
 // empty asm statements pin where the compiler waits for that scalar load
 // (at the end of the iteration, not right after issuing it).
 // With BOUNDED, exactly `count` instructions run (a subtree's code range,
-// which has no END of its own); otherwise the program runs up to its END.
+// which has no END of its own); otherwise the program runs up to the word
+// that carries the stop action (its last) or an END.
+// DUAL (forward programs only) applies a word's second action; gradient
+// programs hold capture levels in those bits.
 // run_from takes the first instruction word already loaded (`first`, equal
 // to prog[0]); run_program loads it.
 // With CAPTURE (the adjoint's runs), after every word whose capture level
@@ -121,14 +171,16 @@ typedef const __attribute__((address_space(4))) unsigned long long* prog_ptr;
 // value c sits at cap[c * K * 64 + j * 64] (cap offset by the lane), *csp
 // counts the values, and pushes beyond cap_limit are dropped (the plan sizes
 // every tree's sweep within the limit).
-template <int K, int VM, int NO, bool BOUNDED = false, bool CAPTURE = false>
+template <int K, int VM, int NO, bool BOUNDED = false, bool CAPTURE = false, bool DUAL = false>
 __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first, Regs<K, VM, NO>& s, float* spill,
                                          int count = 0, float* cap = nullptr, int* csp = nullptr, int cap_level = 0,
                                          int cap_limit = 0) {
   if (BOUNDED && count <= 0) return;
   // `first` is wave-uniform; say so, so that it can live in scalar registers
-  unsigned long long ins = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)first) |
-                           ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(first >> 32)) << 32);
+  // (the builtin returns int: widen the low half through uint32_t, or a word with bit 31 set
+  // would fill the payload half with ones)
+  unsigned long long ins = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)first) |
+                           ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(first >> 32)) << 32);
   asm volatile("" : "+s"(ins));
   int left = count;
   // one exit (after the latch), so the loop is a single-entry single-exit
@@ -213,11 +265,8 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     _Pragma("unroll") for (int j = 0; j < K; ++j) s.r[j] = bin_op<(B)>(s.T[j], s.A[j]);     \
     break;
 
-// Unary (transcendental) functions are applied after the switch, from the
-// word's action bits: the library implementations branch per lane, and
-// keeping those divergent branches out of the dispatch switch keeps the
-// switch a purely scalar branch tree (no per-lane flow merges that copy the
-// register state).
+// Unary functions are applied after the switch, from the word's action bits
+// (apply_unary).
     switch (c) {
       TGP_SRC_CASES(kLD, s.A[j] = v)
       TGP_SRC_CASES(kTLD, s.T[j] = v)
@@ -253,48 +302,13 @@ __device__ __forceinline__ void run_from(prog_ptr prog, unsigned long long first
     // keep act an opaque scalar: otherwise the compiler threads the per-case
     // constants through boolean phis held as 64-bit lane masks
     asm volatile("" : "+s"(act));
-    if (act) {
-      if (act & kActUn) {
-        // f(A) in place; a Modi node's value goes to r while A keeps the
-        // child value it hands up
-        float keep[K];
-        if (act & kActModi) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) keep[j] = s.A[j];
-        }
-        switch (act & 7) {
-          case 0:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<0>(s.A[j]);
-            break;
-          case 1:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<1>(s.A[j]);
-            break;
-          case 2:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<2>(s.A[j]);
-            break;
-          case 3:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<3>(s.A[j]);
-            break;
-          case 4:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<4>(s.A[j]);
-            break;
-          default:
-#pragma unroll
-            for (int j = 0; j < K; ++j) s.A[j] = un_op<5>(s.A[j]);
-            break;
-        }
-        if (act & kActModi) {
-#pragma unroll
-          for (int j = 0; j < K; ++j) {
-            s.r[j] = s.A[j];
-            s.A[j] = keep[j];
-          }
-        }
+    if (act & kActUn) {
+      apply_unary<K, VM, NO>(s, act);
+      // DUAL (forward programs): the word's second action
+      if (DUAL && (w & kAct2Flag)) {
+        int un2 = act2_of(w);
+        asm volatile("" : "+s"(un2));
+        apply_unary<K, VM, NO>(s, un2);
       }
     }
     if constexpr (CAPTURE) {

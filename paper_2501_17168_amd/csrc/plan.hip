@@ -74,6 +74,17 @@ __device__ __forceinline__ bool folds_into_child(int r, int rc1, bool adj) {
          rec_arity(rc1) == 2;
 }
 
+// Forward programs: a unary node r over a non-Modi unary node (record rc1)
+// whose own child (record rc2) is a leaf or a binary node takes the second
+// action of the word that carries its child's function (the child's load, or
+// the binary node's last word), and emits nothing of its own but its ACC
+// when it is a Modi node. Longer unary chains pair up only at their bottom;
+// the nodes above keep NOP words.
+__device__ __forceinline__ bool folds_second(int r, int rc1, int rc2, bool adj) {
+  return !adj && rec_kind(r) == kTypeFunc && rec_arity(r) == 1 && rec_kind(rc1) == kTypeFunc &&
+         rec_arity(rc1) == 1 && rec_modi(rc1) < 0 && (rec_kind(rc2) != kTypeFunc || rec_arity(rc2) == 2);
+}
+
 // action bits of a unary node: its function, for the Modi register if Modi
 __device__ __forceinline__ int unary_act(int op, int mo) {
   return kActUn | un_index(op) | (mo >= 0 ? kActModi : 0);
@@ -452,7 +463,10 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           if (rec_kind(r) == kTypeFunc) {
             const int c1 = i + 1;
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
-            int cc = own_code(r) - (folds_into_child(r, s_rec[c1], a.adj) ? 1 : 0);
+            const bool un1 = rec_kind(s_rec[c1]) == kTypeFunc && rec_arity(s_rec[c1]) == 1;
+            const bool folded = folds_into_child(r, s_rec[c1], a.adj) ||
+                                (un1 && folds_second(r, s_rec[c1], s_rec[c1 + 1], a.adj));
+            int cc = own_code(r) - (folded ? 1 : 0);
             if (rec_arity(r) == 2) {
               const int r2 = s_rec[c1 + s_sz[c1]];
               const bool l2 = rec_kind(r2) != kTypeFunc;
@@ -584,7 +598,8 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int c1 = i + 1;
       const int r1 = s_rec[c1];
       const bool l1 = rec_kind(r1) != kTypeFunc;
-      const bool folded = folds_into_child(r, r1, a.adj);
+      const bool un1 = !l1 && rec_arity(r1) == 1;
+      const bool folded = folds_into_child(r, r1, a.adj) || (un1 && folds_second(r, r1, s_rec[c1 + 1], a.adj));
       const int oc = own_code(r) - (folded ? 1 : 0);
       const int pos = st + cs - oc;  // first own instruction
       if (folded) {
@@ -599,6 +614,11 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           int src;
           leaf_src(r1, vrow[c1], src, pay);
           wd = load_word(src, unary_act(op, mo), s_pre[pos]);
+          // the function of a unary parent (node i - 1) as the second action
+          if (i > 0 && folds_second(s_rec[i - 1], r, r1, a.adj)) {
+            const int rp = s_rec[i - 1];
+            wd = with_act2(wd, unary_act(rec_op(rp), rec_modi(rp)));
+          }
         }
         emit(pos, mo >= 0 ? wd : cap(wd), pay);
         if (mo >= 0) emit(pos + 1, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
@@ -611,8 +631,14 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       // the function of a unary parent folded into this node's last word (node i - 1 is the
       // parent exactly when it is a unary function node)
       const int rp = i > 0 ? s_rec[i - 1] : 0;
-      const uint32_t pact =
+      uint32_t pact =
           (i > 0 && folds_into_child(rp, r, a.adj)) ? (uint32_t)unary_act(rec_op(rp), rec_modi(rp)) << kActShift : 0u;
+      // and the function of a unary grandparent (node i - 2) over a non-Modi unary parent as the
+      // second action
+      if (i > 1 && folds_second(s_rec[i - 2], rp, r, a.adj)) {
+        const int rg = s_rec[i - 2];
+        pact = with_act2(pact, unary_act(rec_op(rg), rec_modi(rg)));
+      }
       int src, aux = 0;
       float pay = 0.0f;
       bool a_first;  // A holds the first operand and src the second

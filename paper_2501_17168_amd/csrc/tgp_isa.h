@@ -73,6 +73,11 @@ constexpr int kSrcC = 0, kSrcR0 = 1, kSrcRM = 5, kSrcX0 = 6, kNumSrc = 22;
 //           the level is the light depth of the node's parent (below). Only
 //           the adjoint's interpreter reads these bits: a run at level l
 //           pushes A on the capture stack after every word whose level is l.
+//           Forward programs (never captured) use the same bits for a second
+//           action: bit 13 set, the 4-bit field holding a unary index
+//           (bits 0..2) and kActModi; it applies after the first action (a
+//           unary node over a unary node whose function rides on a load or
+//           on a binary node's last word).
 constexpr int kLD = 0;                    // A = src
 constexpr int kTLD = kLD + kNumSrc;       // T = src
 constexpr int kADD = kTLD + kNumSrc;      // A = A + src
@@ -110,6 +115,10 @@ __host__ __device__ constexpr uint32_t with_capture(uint32_t w, int level) {
   return w | kCapFlag | ((uint32_t)(level & 3) << 14) | ((uint32_t)(level >> 2) << 30);
 }
 __host__ __device__ constexpr int capture_level(uint32_t w) { return (int)(((w >> 14) & 3u) | ((w >> 28) & 12u)); }
+// the second action of a forward-program word (act = kActUn | index, with kActModi for a Modi node)
+constexpr uint32_t kAct2Flag = kCapFlag;
+__host__ __device__ constexpr uint32_t with_act2(uint32_t w, int act) { return with_capture(w, act & 15); }
+__host__ __device__ constexpr int act2_of(uint32_t w) { return kActUn | capture_level(w); }
 
 // ---- per-tree plan record (int32 fields) ----
 // info[t*kInfoStride + k]

@@ -277,3 +277,87 @@ def test_strided_rows_and_views():
     Xw[:, :w.D] = torch.from_numpy(w.X).to(DEV)
     got = device_fit(pop, Xw[:, :w.D], torch.from_numpy(Y).to(DEV), 1)
     compare_fitness(got, oracle_fit("plain", w, Y), label="strided")
+
+
+def _encode(node, rows):
+    """Prefix-encode a nested tuple tree into (type, value, size) rows: ("x", i), ("c", v) or
+    ("f", op, modi_output_or_None, *children)."""
+    t, v, s = rows
+    k = len(t)
+    t.append(0.0); v.append(0.0); s.append(0.0)
+    if node[0] == "x":
+        t[k], v[k] = 0.0, float(node[1])
+    elif node[0] == "c":
+        t[k], v[k] = 1.0, float(node[1])
+    else:
+        t[k] = 2.0 if node[2] is None else 3.0 + node[2]
+        v[k] = float(node[1])
+        for ch in node[3:]:
+            _encode(ch, rows)
+    s[k] = float(len(t) - k)
+
+
+def _folding_trees():
+    """Trees for every way a unary node is folded into the forward program: into its binary
+    child's last word (a fused op word, a pre-loaded one, a Modi child's ACC), as the second action
+    of a load (of a constant or a variable) or of a binary node's last word, Modi or not, at the
+    program's first word or after a spill, chains of 2 to 5 unary nodes, a folded root (whose
+    child's word then ends the program) and leaf roots."""
+    SIN, COS, TANH, EXP, LOG, TAN = 4, 5, 6, 7, 8, 11
+    ADD, SUB, MUL, DIV, MAX = 0, 1, 2, 3, 9
+    x = lambda i: ("x", i)
+    c = lambda v: ("c", v)
+    f = lambda op, *ch, m=None: ("f", op, m, *ch)
+    big = f(MUL, f(MUL, x(0), x(1)), f(ADD, x(2), x(0)))
+    return [
+        f(EXP, f(ADD, f(SIN, f(SIN, c(-4.537)), m=2), f(TANH, f(TANH, x(2), m=1))), m=0),
+        f(EXP, f(SIN, f(LOG, f(LOG, x(1))))),
+        f(SIN, f(COS, f(ADD, c(0.3), c(0.9)))),
+        f(SIN, f(COS, f(MUL, x(0), c(0.5)))),
+        f(ADD, f(TANH, f(EXP, f(DIV, x(0), x(1))), m=1), x(2)),
+        f(TAN, f(SUB, x(0), x(1))),
+        f(COS, f(SIN, f(ADD, x(0), x(1)), m=1), m=2),
+        f(SIN, f(ADD, x(0), x(1), m=0)),
+        f(LOG, c(2.5)),
+        f(EXP, f(LOG, c(-3.0), m=1), m=0),
+        f(SIN, f(COS, f(TANH, f(EXP, f(LOG, f(MUL, x(0), x(1))))))),
+        c(1.25),
+        x(2),
+        f(ADD, big, f(SIN, f(COS, c(0.7)))),
+        f(ADD, big, f(SIN, f(COS, c(-1.1)), m=2)),
+        f(MAX, big, f(TANH, f(COS, f(SUB, x(1), c(0.25))), m=1), m=0),
+        f(SIN, f(COS, f(TANH, c(0.4)))),
+        f(EXP, f(TANH, f(ADD, x(0), x(1), m=2), m=1)),
+    ]
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_unary_folding_patterns(mode):
+    """Every prediction of the folding trees inside its float32 envelope (and close to float64),
+    under each schedule; the first-word constant loads carry a second Modi action, whose word has
+    bit 31 set."""
+    trees = _folding_trees()
+    L = 32
+    T = np.full((len(trees), L), np.nan, np.float32)
+    V, S = T.copy(), T.copy()
+    for p, tr in enumerate(trees):
+        rows = ([], [], [])
+        _encode(tr, rows)
+        n = len(rows[0])
+        T[p, :n], V[p, :n], S[p, :n] = rows
+    rng = np.random.default_rng(11)
+    D = 700
+    X = rng.uniform(-2.0, 2.0, (3, D)).astype(np.float32)
+    pop = tgp.Population(*(torch.from_numpy(a).to(DEV) for a in (T, V, S)))
+    _, pred = tgp.eval_multi_output(pop, torch.from_numpy(X).to(DEV), None, n_out=3, want_pred=True,
+                                    config=tgp.cfg(mode=mode))
+    torch.cuda.synchronize()
+    pred = pred.cpu().numpy().astype(np.float64)
+    ref = O.predict(T, V, S, X, 3)
+    for p in range(len(trees)):
+        outs, _ = E.forward(O.decode(T[p], V[p], S[p], 3, 3), X, 3)
+        for o in range(3):
+            ok = inside(pred[p, o], outs[o].lo, outs[o].hi, outs[o].nan)
+            assert ok.all(), (p, o, np.nonzero(~ok)[0][:5], pred[p, o][~ok][:5], ref[p, o][~ok][:5])
+            scale = np.maximum(np.abs(ref[p, o]), 1.0)
+            assert np.all(np.abs(pred[p, o] - ref[p, o]) <= 1e-4 * scale), (p, o)
