@@ -47,6 +47,9 @@ constexpr int kRecPop = 1 << 20;
 // set on the light child of a node whose children are both function nodes: the smaller one, which
 // the code evaluates second (ties: the second child)
 constexpr int kRecLight = 1 << 21;
+// forward programs: set on a unary node that takes the second action of the word carrying its
+// child's function (pass 3b)
+constexpr int kRecSecond = 1 << 22;
 
 __device__ __forceinline__ bool is_intf(float x) { return isfinite(x) && x == floorf(x); }
 
@@ -72,17 +75,6 @@ __device__ __forceinline__ int own_code(int r) {
 __device__ __forceinline__ bool folds_into_child(int r, int rc1, bool adj) {
   return !adj && rec_kind(r) == kTypeFunc && rec_arity(r) == 1 && rec_kind(rc1) == kTypeFunc &&
          rec_arity(rc1) == 2;
-}
-
-// Forward programs: a unary node r over a non-Modi unary node (record rc1)
-// whose own child (record rc2) is a leaf or a binary node takes the second
-// action of the word that carries its child's function (the child's load, or
-// the binary node's last word), and emits nothing of its own but its ACC
-// when it is a Modi node. Longer unary chains pair up only at their bottom;
-// the nodes above keep NOP words.
-__device__ __forceinline__ bool folds_second(int r, int rc1, int rc2, bool adj) {
-  return !adj && rec_kind(r) == kTypeFunc && rec_arity(r) == 1 && rec_kind(rc1) == kTypeFunc &&
-         rec_arity(rc1) == 1 && rec_modi(rc1) < 0 && (rec_kind(rc2) != kTypeFunc || rec_arity(rc2) == 2);
 }
 
 // action bits of a unary node: its function, for the Modi register if Modi
@@ -451,6 +443,35 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
     }
     max_stack = wave_max(best);
 
+    // ---- pass 3b (forward programs): second actions along unary chains ----
+    // A unary node whose child is a non-Modi unary node is linked to it. The
+    // bottom of a run of linked nodes puts its function on a load, on its
+    // binary child's last word or on a NOP of its own, as that word's first
+    // action; the node above it takes the same word's second action, the one
+    // above that emits a NOP, and so on: node i takes a second action when
+    // d(i), the number of linked nodes from i down the run, is odd. Runs are
+    // contiguous in prefix order, so d comes from a ballot of the unlinked
+    // nodes per chunk, chunks taken last to first.
+    if (!a.adj) {
+      int carry = 0;  // d of the first node of the chunk after this one
+      for (int ch = nch - 1; ch >= 0; --ch) {
+        const int i = ch * kWave + lane;
+        bool link = false;
+        if (i < len) {
+          const int r = s_rec[i];
+          if (rec_kind(r) == kTypeFunc && rec_arity(r) == 1) {
+            const int rc = s_rec[i + 1];
+            link = rec_kind(rc) == kTypeFunc && rec_arity(rc) == 1 && rec_modi(rc) < 0;
+          }
+        }
+        const unsigned long long stop = __builtin_amdgcn_ballot_w64(!link);
+        const unsigned long long ahead = stop >> lane;  // unlinked nodes at or after node i
+        const int d = ahead ? __builtin_ctzll(ahead) : (kWave - lane) + carry;
+        if (link && (d & 1)) s_rec[i] |= kRecSecond;
+        carry = stop ? __builtin_ctzll(stop) : kWave + carry;
+      }
+    }
+
     // ---- pass 4: code size and function count of every subtree ----
     // E[i] = sum over nodes j < i of (code words node j emits | 1 << 16 if j is a function)
     {
@@ -463,9 +484,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           if (rec_kind(r) == kTypeFunc) {
             const int c1 = i + 1;
             const bool l1 = rec_kind(s_rec[c1]) != kTypeFunc;
-            const bool un1 = rec_kind(s_rec[c1]) == kTypeFunc && rec_arity(s_rec[c1]) == 1;
-            const bool folded = folds_into_child(r, s_rec[c1], a.adj) ||
-                                (un1 && folds_second(r, s_rec[c1], s_rec[c1 + 1], a.adj));
+            const bool folded = folds_into_child(r, s_rec[c1], a.adj) || (r & kRecSecond);
             int cc = own_code(r) - (folded ? 1 : 0);
             if (rec_arity(r) == 2) {
               const int r2 = s_rec[c1 + s_sz[c1]];
@@ -598,8 +617,7 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int c1 = i + 1;
       const int r1 = s_rec[c1];
       const bool l1 = rec_kind(r1) != kTypeFunc;
-      const bool un1 = !l1 && rec_arity(r1) == 1;
-      const bool folded = folds_into_child(r, r1, a.adj) || (un1 && folds_second(r, r1, s_rec[c1 + 1], a.adj));
+      const bool folded = folds_into_child(r, r1, a.adj) || (r & kRecSecond);
       const int oc = own_code(r) - (folded ? 1 : 0);
       const int pos = st + cs - oc;  // first own instruction
       if (folded) {
@@ -614,11 +632,11 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
           int src;
           leaf_src(r1, vrow[c1], src, pay);
           wd = load_word(src, unary_act(op, mo), s_pre[pos]);
-          // the function of a unary parent (node i - 1) as the second action
-          if (i > 0 && folds_second(s_rec[i - 1], r, r1, a.adj)) {
-            const int rp = s_rec[i - 1];
-            wd = with_act2(wd, unary_act(rec_op(rp), rec_modi(rp)));
-          }
+        }
+        // the function of a unary parent (node i - 1) that takes the second action
+        if (i > 0 && (s_rec[i - 1] & kRecSecond)) {
+          const int rp = s_rec[i - 1];
+          wd = with_act2(wd, unary_act(rec_op(rp), rec_modi(rp)));
         }
         emit(pos, mo >= 0 ? wd : cap(wd), pay);
         if (mo >= 0) emit(pos + 1, cap(mkword(kACC)), __uint_as_float((uint32_t)mo));
@@ -633,9 +651,9 @@ __global__ __launch_bounds__(64) void plan_kernel(PlanArgs a) {
       const int rp = i > 0 ? s_rec[i - 1] : 0;
       uint32_t pact =
           (i > 0 && folds_into_child(rp, r, a.adj)) ? (uint32_t)unary_act(rec_op(rp), rec_modi(rp)) << kActShift : 0u;
-      // and the function of a unary grandparent (node i - 2) over a non-Modi unary parent as the
+      // and the function of a unary grandparent (node i - 2, over the unary parent) that takes the
       // second action
-      if (i > 1 && folds_second(s_rec[i - 2], rp, r, a.adj)) {
+      if (i > 1 && (s_rec[i - 2] & kRecSecond)) {
         const int rg = s_rec[i - 2];
         pact = with_act2(pact, unary_act(rec_op(rg), rec_modi(rg)));
       }
