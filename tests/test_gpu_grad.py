@@ -307,3 +307,55 @@ def test_multi_output_gradients_long_trees():
     modi = np.asarray(w.meta["modi_trees"])
     assert np.any(gv[modi][ref.const[modi]] != 0)
     assert rep_v["tight"] >= 0.1 * rep_v["n"], rep_v
+
+
+def _complete_tree_var_const(depth, rng, Lmax):
+    """Complete binary tree of the given depth over + - * (mostly + and -, so values stay finite);
+    every bottom node combines a variable (first child) and a constant (second child)."""
+    nodes = []
+
+    def rec(d, first):
+        if d == depth:
+            nodes.append((0, int(rng.integers(0, 2)), 1) if first else (1, float(rng.uniform(-1, 1)), 1))
+            return 1
+        i = len(nodes)
+        nodes.append(None)
+        n = 1 + rec(d + 1, True) + rec(d + 1, False)
+        nodes[i] = (2, int(rng.choice([0, 1, 2], p=[0.45, 0.45, 0.1])), n)
+        return n
+
+    rec(0, True)
+    t = np.full(Lmax, np.nan, np.float32)
+    v, s = t.copy(), t.copy()
+    for i, (a, b, c) in enumerate(nodes):
+        t[i], v[i], s[i] = a, b, c
+    return t, v, s
+
+
+def test_deep_complete_trees_gradients():
+    """Complete trees of depth 8 and 9 (up to 1,023 nodes) whose bottom nodes combine a variable
+    and a constant: each bottom node is one word (the variable pre-loaded, the constant in the
+    payload) and carries the capture level of its parent, up to 9. Runs of the sweeps then start on
+    words whose level sets bit 31, with a constant payload that must survive the interpreter's
+    widening of its first word. Both sweeps, 2 to 4 points per lane; fitness and gradients inside
+    the oracle's envelopes."""
+    r = np.random.default_rng(21)
+    Lmax = 1024
+    rows = [_complete_tree_var_const(9, r, Lmax) for _ in range(3)] + [_complete_tree_var_const(8, r, Lmax)]
+    T, V, S = (np.stack([x[i] for x in rows]) for i in range(3))
+    D = 300
+    X = r.uniform(-1, 1, (2, D)).astype(np.float32)
+    Y = r.normal(size=(1, D)).astype(np.float32)
+    pop = tgp.Population(*(torch.from_numpy(a).to(DEV) for a in (T, V, S)))
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    fref = FitnessRef(T, V, S, X, Y)
+    ref = GradRef(T, V, S, X, Y)
+    for k in (2, 3, 4):
+        for flags in (0, 4):
+            label = f"complete K={k} flags={flags}"
+            mse, gv, gx = (t.cpu().numpy() for t in
+                           tgp.eval_mse_grad(pop, Xd, Yd, config=tgp.cfg(mode=2, points_per_lane=k, flags=flags)))
+            assert np.isfinite(mse).all(), label
+            compare_fitness(mse, fref, label=label)
+            compare_grad_value(gv, ref, label=label)
+            compare_grad_x(gx, ref, label=label)
